@@ -1,0 +1,251 @@
+/*
+ * lsplat: tile-based differentiable rasterizer for 3D Linear Splatting
+ * (Chen et al., "Beyond Gaussians: Fast and High-Fidelity 3D Splatting with
+ * Linear Kernels", arXiv 2411.12440), for AMD MI355X (gfx950).
+ *
+ * C ABI.  No HIP or PyTorch types appear in these signatures: device memory
+ * is passed as plain pointers, streams as an opaque `void*` holding a
+ * hipStream_t (NULL = the null stream).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers are DEVICE pointers unless a field is named h_*, which is HOST
+ *    memory read during the call only.
+ *  - The caller allocates and owns every buffer, including the workspace;
+ *    the library keeps no pointer after the call returns and frees nothing.
+ *  - Calls only enqueue work on the given stream (asynchronous, no host
+ *    synchronisation).  Buffers must stay valid until that work completes.
+ *  - Argument errors are detected on the host before any launch and return a
+ *    negative ls_status; ls_last_error() then describes the problem.  HIP
+ *    launch failures return LS_ERR_HIP.
+ *  - Splat attributes are FP32 structure-of-arrays ("planar"): a field with
+ *    components [d][n] stores component 0 of all n splats, then component 1...
+ *  - Images are planar per camera: camera c owns 3*H_c*W_c floats (R plane,
+ *    G plane, B plane, each row-major H_c x W_c), cameras concatenated in
+ *    order.  Per-pixel arrays (final_T, last) hold H_c*W_c entries per camera,
+ *    concatenated.
+ *  - (camera, splat) pairs are numbered camera-major: pair index m of splat i
+ *    of camera c is pair_off[c] + (i - first splat of c's scene), where
+ *    pair_off[c] is the sum of the scene sizes of cameras 0..c-1.
+ *  - Global tile ids are tile_off[c] + ty * GX_c + tx with GX_c = ceil(W_c/tile_w),
+ *    GY_c = ceil(H_c/tile_h), tile_off[c] = sum over earlier cameras of GX*GY.
+ */
+#ifndef LSPLAT_H
+#define LSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LSPLAT_VERSION 100
+
+typedef enum {
+  LS_OK = 0,
+  LS_ERR_INVALID_ARG = -1,   /* bad pointer, size, flag or shape */
+  LS_ERR_CAPACITY = -2,      /* intersection capacity provably too small */
+  LS_ERR_HIP = -3,           /* a HIP call or kernel launch failed */
+  LS_ERR_UNSUPPORTED = -4,   /* a valid request this build does not implement */
+  LS_ERR_WORKSPACE = -5      /* workspace pointer/size does not match the plan */
+} ls_status;
+
+/*
+ * Rasterizer settings (host struct, read during the call only).
+ *
+ * lambda     Distribution-alignment factor of Eq. 12 (Sec. 3.3.1): the kernel
+ *            is L' = max(0, 1 - D'/lambda) with D' the 2D Mahalanobis distance
+ *            of Eq. 11.  The paper uses 2.5; 1.0 is the plain kernel of Eq. 10.
+ *            Must be > 0.
+ * ags        1: adaptive gradient scaling of Eq. 13-14 (Sec. 3.3.2) in the
+ *            backward pass.  The forward pass is unchanged.
+ * ags_arg    0: omega = exp(-D'^2) (raw distance, default); 1: exp(-(D'/lambda)^2).
+ * ags_scope  0: omega scales only the gradient through L' into the splat
+ *            geometry (default); 1: omega scales every gradient of the pair.
+ * eps2d      Dilation added to the diagonal of the 2D covariance (> 0).
+ * alpha_min  A splat whose alpha is below this is skipped (default 1/255).
+ * alpha_max  alpha = min(alpha_max, o * L') (default 0.99; in (0, 1)).
+ * t_min      A splat that would take the transmittance below t_min stops the
+ *            pixel and is not added (default 1e-4).  The three blending rules
+ *            are the 3DGS ones the paper keeps unchanged (Sec. 3.2).
+ * near_z, far_z  A splat centre outside (near_z, far_z) in camera z is culled.
+ * clip       The tangent used in the projection Jacobian is clamped to
+ *            clip * (half field of view) (default 1.3).
+ * bg         Background colour added as T_final * bg.
+ * sh_degree  Degree 0..3 of the real spherical-harmonics colour.
+ * tile_w, tile_h  Tile shape in pixels: 16x16, 16x8, 8x8 or 32x8.
+ * batch      Splats staged in LDS per batch in the raster kernels: 0 (= the
+ *            tile's pixel count), 64, 128 or 256; must not exceed the tile's
+ *            pixel count.
+ */
+typedef struct ls_config {
+  float lambda;
+  float eps2d;
+  float alpha_min, alpha_max, t_min;
+  float near_z, far_z, clip;
+  float bg[3];
+  int32_t ags, ags_arg, ags_scope;
+  int32_t sh_degree;
+  int32_t tile_w, tile_h;
+  int32_t batch;
+} ls_config;
+
+/*
+ * Splats of one or more scenes, concatenated (Sec. 3.1: centre mu, scale S and
+ * rotation R with Sigma = R S S^T R^T (Eq. 2), opacity o, colour c (Eq. 6)).
+ * n        total splats over all scenes.
+ * means    [3][n] world-space centres.
+ * scales   [3][n] per-axis scales, > 0 (activated, not log).
+ * quats    [4][n] rotation quaternions (w, x, y, z), any non-zero norm.
+ * opacity  [n] in (0, 1) (activated, not logit).
+ * sh       [K][3][n] SH coefficients, K = (sh_degree + 1)^2, band-major then
+ *          channel.
+ */
+typedef struct ls_splats {
+  int64_t n;
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacity;
+  const float* sh;
+} ls_splats;
+
+/* Gradients w.r.t. the ls_splats fields, same shapes (written, not added). */
+typedef struct ls_grads {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacity;
+  float* sh;
+} ls_grads;
+
+/*
+ * Cameras (Sec. 3.1, Eq. 3: world-to-camera W and the local affine Jacobian J
+ * of the pinhole map).  OpenCV axes: x right, y down, z forward.  Pixel
+ * (px, py) samples the point (px + 0.5, py + 0.5).
+ * viewmat            device [C][3][4] world->camera (rotation | translation).
+ * intrin             device [C][4] (fx, fy, cx, cy).
+ * h_width, h_height  host [C] image size in pixels (>= 1).
+ * h_scene_of_cam     host [C] scene index of each camera (0..n_scenes-1).
+ * h_scene_splat_off  host [n_scenes + 1] first splat of each scene in the
+ *                    concatenated ls_splats, increasing, last = n.
+ */
+typedef struct ls_cameras {
+  int32_t n_cams;
+  int32_t n_scenes;
+  const float* viewmat;
+  const float* intrin;
+  const int32_t* h_width;
+  const int32_t* h_height;
+  const int32_t* h_scene_of_cam;
+  const int64_t* h_scene_splat_off;
+} ls_cameras;
+
+/*
+ * Byte offsets (from the workspace base) and element counts of the arrays the
+ * library keeps in the caller's workspace.  Filled by ls_workspace_layout;
+ * exposed so that callers and tests can read intermediate results.
+ *   M = number of (camera, splat) pairs, T = total tiles, cap = capacity.
+ *   proj       [M] 64-byte records: double mean2d[2], double conic[3]
+ *              (A, B, C with D'^2 = A dx^2 + 2B dx dy + C dy^2), float rgb[3],
+ *              float opacity, 8 bytes padding.
+ *   rect       [M] uint16 x4: tile rectangle (tx0, ty0, tx1, ty1) inclusive.
+ *   ntiles     [M] uint32: tiles touched (0 = culled).
+ *   depth_key  [M] uint32: FP32 bit pattern of camera-space z (0xFFFFFFFF if
+ *              culled).
+ *   order      [M] uint32: pair ids sorted by (depth_key, pair id).
+ *   isect_off  [M+1] int64: exclusive scan of ntiles in `order`.
+ *   keys       [cap] uint32: sorted global tile ids.
+ *   vals       [cap] uint32: pair ids in (tile, depth, pair id) order.
+ *   ranges     [T+1] int64: tile t owns sorted positions [ranges[t], ranges[t+1]).
+ *   n_isect    int64 scalar: true intersection count (may exceed cap).
+ *   grad2d     [M][9] float: per-pair 2D gradient sums (backward).
+ */
+typedef struct ls_layout {
+  int64_t n_pairs, n_tiles, n_pixels, capacity;
+  size_t total_bytes;
+  size_t cams, proj, rect, ntiles, depth_key, order, isect_off, keys, vals, ranges,
+      n_isect, grad2d;
+  size_t scratch;   /* library-internal (sort buffers, histograms) */
+} ls_layout;
+
+/* Library version (LSPLAT_VERSION). */
+int ls_version(void);
+
+/* Text of the last error on the calling thread; valid until the next call. */
+const char* ls_last_error(void);
+
+/*
+ * Workspace needed for these cameras and settings with room for
+ * `isect_capacity` (>= 0) (tile, splat) intersections.  Host-only.
+ */
+ls_status ls_workspace_size(const ls_config* cfg, const ls_cameras* cams,
+                            int64_t isect_capacity, size_t* bytes);
+
+/* Same plan, with the offset of every array (see ls_layout).  Host-only. */
+ls_status ls_workspace_layout(const ls_config* cfg, const ls_cameras* cams,
+                              int64_t isect_capacity, ls_layout* out);
+
+/*
+ * Projection (Sec. 3.1, Eq. 2-4; kernel support from Eq. 11-12).  For every
+ * (camera, splat) pair: covariance Sigma = R S S^T R^T, camera-space centre,
+ * projected centre, dilated 2D covariance Sigma_2D = (J W Sigma W^T J^T)_2x2
+ * + eps2d I and its inverse, SH colour, and the tile rectangle that bounds
+ * the support ellipse D' < lambda.  Writes proj, rect, ntiles and depth_key of
+ * the workspace.  Geometry that feeds rasterization is computed in FP64;
+ * rect, ntiles and depth_key follow a fixed FP32 operation sequence (no fused
+ * multiply-add, correctly rounded division and square root) so that they are
+ * reproducible bit for bit.
+ */
+ls_status ls_project(const ls_config* cfg, const ls_splats* splats, const ls_cameras* cams,
+                     void* ws, size_t ws_bytes, int64_t isect_capacity, void* stream);
+
+/*
+ * Binning: order pairs front to back by (depth_key, pair id), scan their tile
+ * counts, write one (global tile, pair) entry per touched tile, stably radix
+ * sort the entries by tile id, and compute each tile's range.  The result is
+ * every tile's list in ascending (depth_key, pair id) order.  The paper keeps
+ * this stage of the 3DGS pipeline (Sec. 3.2, Sec. 4.1) without describing it.
+ * n_isect always receives the true count; when it exceeds the capacity,
+ * nothing past the capacity is written, the sort is skipped and the
+ * rasterizer calls of this workspace produce no output: read n_isect, grow
+ * the capacity and run again.  Requires a preceding ls_project on `ws`.
+ */
+ls_status ls_bin_sort(const ls_config* cfg, const ls_cameras* cams, void* ws, size_t ws_bytes,
+                      int64_t isect_capacity, void* stream);
+
+/*
+ * Forward compositing (Eq. 6 with the linear kernel of Eq. 10-12): for each
+ * pixel, walk its tile's list front to back, alpha = min(alpha_max,
+ * o * max(0, 1 - D'/lambda)), skip alpha < alpha_min, stop before a splat
+ * that would take T below t_min, C += c alpha T, T *= (1 - alpha).
+ * image    [sum_c 3 H_c W_c] out: C + T_final * bg.
+ * final_T  [P] out: final transmittance.
+ * last     [P] out: 1 + position in the tile list of the last contributing
+ *          splat (0 if none); the backward pass starts there.
+ */
+ls_status ls_rasterize_fwd(const ls_config* cfg, const ls_cameras* cams, void* ws,
+                           size_t ws_bytes, int64_t isect_capacity, float* image,
+                           float* final_T, int32_t* last, void* stream);
+
+/*
+ * Backward pass of ls_rasterize_fwd and ls_project.  Walks each tile's list
+ * back to front from `last`, recovering the transmittance by division
+ * (T_i = T_{i+1} / (1 - alpha_i)), accumulates per-pair 2D gradients (with
+ * adaptive gradient scaling, Eq. 13-14, when cfg->ags), then applies the
+ * chain rule through the projection and sums over cameras.
+ * final_T, last  from the forward call on the same workspace and settings.
+ * dL_dimage      [sum_c 3 H_c W_c] upstream gradient.
+ * grads          out: written (not accumulated) for every splat.
+ */
+ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* splats,
+                           const ls_cameras* cams, void* ws, size_t ws_bytes,
+                           int64_t isect_capacity, const float* final_T, const int32_t* last,
+                           const float* dL_dimage, const ls_grads* grads, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSPLAT_H */

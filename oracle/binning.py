@@ -154,3 +154,16 @@ def tile_ranges(sorted_gtile, n_tiles_total):
     off = np.zeros(n_tiles_total + 1, np.int64)
     off[1:] = np.cumsum(counts)
     return off
+
+
+def tile_list(rect, ntiles, depth_key, gtile, lay):
+    """One tile's list by its plain definition: the pairs of the tile's camera
+    whose rectangle contains the tile, in (depth key, pair id) order."""
+    c = int(np.searchsorted(lay.tile_off, gtile, side="right") - 1)
+    gx = lay.grid[c][0]
+    ty, tx = divmod(int(gtile - lay.tile_off[c]), gx)
+    m0, m1 = int(lay.pair_off[c]), int(lay.pair_off[c + 1])
+    r = rect[m0:m1]
+    sel = (ntiles[m0:m1] > 0) & (r[:, 0] <= tx) & (tx <= r[:, 2]) & (r[:, 1] <= ty) & (ty <= r[:, 3])
+    ids = m0 + np.nonzero(sel)[0]
+    return ids[np.lexsort((ids, depth_key[ids].astype(np.int64)))]

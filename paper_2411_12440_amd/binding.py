@@ -1,0 +1,180 @@
+"""ctypes binding of liblsplat (include/lsplat.h): argument marshalling only.
+
+Every function here takes torch tensors already on the GPU (or host arrays for
+the h_* camera fields), builds the C structs and calls the entry point of the
+same name.  No step of the rasterizer runs in Python; if the shared library is
+missing the import of this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsplat.so")
+
+LS_OK = 0
+_STATUS = {0: "LS_OK", -1: "LS_ERR_INVALID_ARG", -2: "LS_ERR_CAPACITY", -3: "LS_ERR_HIP",
+           -4: "LS_ERR_UNSUPPORTED", -5: "LS_ERR_WORKSPACE"}
+
+
+class LsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("lambda_", C.c_float), ("eps2d", C.c_float), ("alpha_min", C.c_float),
+                ("alpha_max", C.c_float), ("t_min", C.c_float), ("near_z", C.c_float),
+                ("far_z", C.c_float), ("clip", C.c_float), ("bg", C.c_float * 3),
+                ("ags", C.c_int32), ("ags_arg", C.c_int32), ("ags_scope", C.c_int32),
+                ("sh_degree", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("batch", C.c_int32)]
+
+
+class Splats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("scales", C.c_void_p),
+                ("quats", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class Cams(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("n_scenes", C.c_int32), ("viewmat", C.c_void_p),
+                ("intrin", C.c_void_p), ("h_width", C.c_void_p), ("h_height", C.c_void_p),
+                ("h_scene_of_cam", C.c_void_p), ("h_scene_splat_off", C.c_void_p)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("n_tiles", C.c_int64), ("n_pixels", C.c_int64),
+                ("capacity", C.c_int64), ("total_bytes", C.c_size_t), ("cams", C.c_size_t),
+                ("proj", C.c_size_t), ("rect", C.c_size_t), ("ntiles", C.c_size_t),
+                ("depth_key", C.c_size_t), ("order", C.c_size_t), ("isect_off", C.c_size_t),
+                ("keys", C.c_size_t), ("vals", C.c_size_t), ("ranges", C.c_size_t),
+                ("n_isect", C.c_size_t), ("grad2d", C.c_size_t), ("scratch", C.c_size_t)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2411_12440_amd.build` (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    sig = {
+        "ls_version": ([], C.c_int),
+        "ls_last_error": ([], C.c_char_p),
+        "ls_workspace_size": ([P(Config), P(Cams), C.c_int64, P(C.c_size_t)], C.c_int),
+        "ls_workspace_layout": ([P(Config), P(Cams), C.c_int64, P(Layout)], C.c_int),
+        "ls_project": ([P(Config), P(Splats), P(Cams), C.c_void_p, C.c_size_t, C.c_int64,
+                        C.c_void_p], C.c_int),
+        "ls_bin_sort": ([P(Config), P(Cams), C.c_void_p, C.c_size_t, C.c_int64, C.c_void_p],
+                        C.c_int),
+        "ls_rasterize_fwd": ([P(Config), P(Cams), C.c_void_p, C.c_size_t, C.c_int64, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+        "ls_rasterize_bwd": ([P(Config), P(Splats), P(Cams), C.c_void_p, C.c_size_t, C.c_int64,
+                              C.c_void_p, C.c_void_p, C.c_void_p, P(Grads), C.c_void_p], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+LIB = _load()
+EXPORTS = ("ls_version", "ls_last_error", "ls_workspace_size", "ls_workspace_layout",
+           "ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd")
+
+
+def _check(st: int):
+    if st != LS_OK:
+        raise LsError(st, LIB.ls_last_error().decode())
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    return 0 if stream is None else int(stream)
+
+
+class CamerasHost:
+    """Camera metadata: host arrays kept alive for the C struct, plus device
+    tensors for viewmat / intrin."""
+
+    def __init__(self, viewmat, intrin, width, height, scene_of_cam, scene_splat_off):
+        self.viewmat = viewmat        # device float32 [C,3,4] contiguous
+        self.intrin = intrin          # device float32 [C,4]
+        self.h_width = np.ascontiguousarray(width, np.int32)
+        self.h_height = np.ascontiguousarray(height, np.int32)
+        self.h_scene = np.ascontiguousarray(scene_of_cam, np.int32)
+        self.h_off = np.ascontiguousarray(scene_splat_off, np.int64)
+        self.c = Cams(len(self.h_width), len(self.h_off) - 1, _ptr(viewmat), _ptr(intrin),
+                      self.h_width.ctypes.data, self.h_height.ctypes.data,
+                      self.h_scene.ctypes.data, self.h_off.ctypes.data)
+
+
+def make_config(lambda_=2.5, eps2d=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
+                near=0.01, far=1e10, clip=1.3, bg=(0.0, 0.0, 0.0), ags=False, ags_arg=0,
+                ags_scope=0, sh_degree=0, tile_w=16, tile_h=16, batch=0) -> Config:
+    cfg = Config()
+    cfg.lambda_, cfg.eps2d, cfg.alpha_min, cfg.alpha_max, cfg.t_min = lambda_, eps2d, alpha_min, alpha_max, t_min
+    cfg.near_z, cfg.far_z, cfg.clip = near, far, clip
+    for i in range(3):
+        cfg.bg[i] = bg[i]
+    cfg.ags, cfg.ags_arg, cfg.ags_scope = int(ags), ags_arg, ags_scope
+    cfg.sh_degree, cfg.tile_w, cfg.tile_h, cfg.batch = sh_degree, tile_w, tile_h, batch
+    return cfg
+
+
+def splats_struct(n, means, scales, quats, opacity, sh) -> Splats:
+    return Splats(n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh))
+
+
+def grads_struct(means, scales, quats, opacity, sh) -> Grads:
+    return Grads(_ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh))
+
+
+def ls_version() -> int:
+    return LIB.ls_version()
+
+
+def ls_workspace_size(cfg: Config, cams: CamerasHost, capacity: int) -> int:
+    out = C.c_size_t(0)
+    _check(LIB.ls_workspace_size(C.byref(cfg), C.byref(cams.c), capacity, C.byref(out)))
+    return out.value
+
+
+def ls_workspace_layout(cfg: Config, cams: CamerasHost, capacity: int) -> Layout:
+    out = Layout()
+    _check(LIB.ls_workspace_layout(C.byref(cfg), C.byref(cams.c), capacity, C.byref(out)))
+    return out
+
+
+def ls_project(cfg, splats: Splats, cams: CamerasHost, ws, capacity, stream=None):
+    _check(LIB.ls_project(C.byref(cfg), C.byref(splats), C.byref(cams.c), _ptr(ws), ws.numel(),
+                          capacity, _stream(stream)))
+
+
+def ls_bin_sort(cfg, cams: CamerasHost, ws, capacity, stream=None):
+    _check(LIB.ls_bin_sort(C.byref(cfg), C.byref(cams.c), _ptr(ws), ws.numel(), capacity,
+                           _stream(stream)))
+
+
+def ls_rasterize_fwd(cfg, cams: CamerasHost, ws, capacity, image, final_T, last, stream=None):
+    _check(LIB.ls_rasterize_fwd(C.byref(cfg), C.byref(cams.c), _ptr(ws), ws.numel(), capacity,
+                                _ptr(image), _ptr(final_T), _ptr(last), _stream(stream)))
+
+
+def ls_rasterize_bwd(cfg, splats: Splats, cams: CamerasHost, ws, capacity, final_T, last,
+                     dL_dimage, grads: Grads, stream=None):
+    _check(LIB.ls_rasterize_bwd(C.byref(cfg), C.byref(splats), C.byref(cams.c), _ptr(ws),
+                                ws.numel(), capacity, _ptr(final_T), _ptr(last),
+                                _ptr(dL_dimage), C.byref(grads), _stream(stream)))

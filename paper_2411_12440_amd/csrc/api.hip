@@ -1,0 +1,256 @@
+// C-ABI entry points of liblsplat: argument validation, workspace planning and
+// the enqueue of each stage.  Kernels live in project.hip, binsort.hip and
+// raster.hip.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace lsplat {
+
+static thread_local char g_err[512] = "";
+
+static ls_status fail(ls_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+static ls_status hip_fail(hipError_t e, const char* where) {
+  return fail(LS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static bool tile_shape_ok(int w, int h) {
+  return (w == 16 && h == 16) || (w == 16 && h == 8) || (w == 8 && h == 8) || (w == 32 && h == 8);
+}
+
+static ls_status check_config(const ls_config* c) {
+  if (!c) return fail(LS_ERR_INVALID_ARG, "cfg is NULL");
+  if (!(c->lambda > 0.f) || !(c->lambda < 1e6f)) return fail(LS_ERR_INVALID_ARG, "lambda must be in (0, 1e6)");
+  if (!(c->eps2d > 0.f)) return fail(LS_ERR_INVALID_ARG, "eps2d must be > 0");
+  if (!(c->alpha_max > 0.f && c->alpha_max < 1.f)) return fail(LS_ERR_INVALID_ARG, "alpha_max must be in (0, 1)");
+  if (!(c->alpha_min >= 0.f && c->alpha_min <= c->alpha_max))
+    return fail(LS_ERR_INVALID_ARG, "alpha_min must be in [0, alpha_max]");
+  if (!(c->t_min >= 0.f && c->t_min < 1.f)) return fail(LS_ERR_INVALID_ARG, "t_min must be in [0, 1)");
+  if (!(c->near_z > 0.f && c->far_z > c->near_z)) return fail(LS_ERR_INVALID_ARG, "need 0 < near_z < far_z");
+  if (!(c->clip > 0.f)) return fail(LS_ERR_INVALID_ARG, "clip must be > 0");
+  for (int i = 0; i < 3; ++i)
+    if (!(c->bg[i] == c->bg[i])) return fail(LS_ERR_INVALID_ARG, "bg must be finite");
+  if (c->ags != 0 && c->ags != 1) return fail(LS_ERR_INVALID_ARG, "ags must be 0 or 1");
+  if (c->ags_arg != 0 && c->ags_arg != 1) return fail(LS_ERR_INVALID_ARG, "ags_arg must be 0 or 1");
+  if (c->ags_scope != 0 && c->ags_scope != 1) return fail(LS_ERR_INVALID_ARG, "ags_scope must be 0 or 1");
+  if (c->sh_degree < 0 || c->sh_degree > 3) return fail(LS_ERR_INVALID_ARG, "sh_degree must be 0..3");
+  if (!tile_shape_ok(c->tile_w, c->tile_h))
+    return fail(LS_ERR_UNSUPPORTED, "tile shape %dx%d not supported (16x16, 16x8, 8x8, 32x8)",
+                c->tile_w, c->tile_h);
+  int pix = c->tile_w * c->tile_h;
+  if (!(c->batch == 0 || c->batch == 64 || c->batch == 128 || c->batch == 256) || c->batch > pix)
+    return fail(LS_ERR_INVALID_ARG, "batch must be 0, 64, 128 or 256 and at most the tile's pixels");
+  return LS_OK;
+}
+
+static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t cap, Plan* p) {
+  ls_status st = check_config(cfg);
+  if (st != LS_OK) return st;
+  if (!cams) return fail(LS_ERR_INVALID_ARG, "cams is NULL");
+  if (cams->n_cams < 1 || cams->n_cams > 65536) return fail(LS_ERR_INVALID_ARG, "n_cams must be 1..65536");
+  if (cams->n_scenes < 1) return fail(LS_ERR_INVALID_ARG, "n_scenes must be >= 1");
+  if (!cams->h_width || !cams->h_height || !cams->h_scene_of_cam || !cams->h_scene_splat_off)
+    return fail(LS_ERR_INVALID_ARG, "camera host arrays must not be NULL");
+  if (cap < 0) return fail(LS_ERR_INVALID_ARG, "isect_capacity must be >= 0");
+  if (cap > (int64_t)0xFFFFFFFFll * 8) return fail(LS_ERR_INVALID_ARG, "isect_capacity too large");
+  const int64_t* so = cams->h_scene_splat_off;
+  if (so[0] != 0) return fail(LS_ERR_INVALID_ARG, "scene_splat_off[0] must be 0");
+  for (int s = 0; s < cams->n_scenes; ++s)
+    if (so[s + 1] < so[s]) return fail(LS_ERR_INVALID_ARG, "scene_splat_off must be non-decreasing");
+  p->C = cams->n_cams;
+  p->S = cams->n_scenes;
+  p->N = so[p->S];
+  p->cap = cap;
+  p->W.resize(p->C); p->H.resize(p->C); p->GX.resize(p->C); p->GY.resize(p->C); p->scene.resize(p->C);
+  p->pair_off.assign(p->C + 1, 0); p->tile_off.assign(p->C + 1, 0); p->pix_off.assign(p->C + 1, 0);
+  p->splat_lo.resize(p->C); p->splat_hi.resize(p->C);
+  p->max_scene = 0;
+  for (int c = 0; c < p->C; ++c) {
+    int w = cams->h_width[c], h = cams->h_height[c], s = cams->h_scene_of_cam[c];
+    if (w < 1 || h < 1 || w > 16384 || h > 16384)
+      return fail(LS_ERR_INVALID_ARG, "camera %d: image size %dx%d outside 1..16384", c, w, h);
+    if (s < 0 || s >= p->S) return fail(LS_ERR_INVALID_ARG, "camera %d: scene %d out of range", c, s);
+    p->W[c] = w; p->H[c] = h; p->scene[c] = s;
+    p->GX[c] = (w + cfg->tile_w - 1) / cfg->tile_w;
+    p->GY[c] = (h + cfg->tile_h - 1) / cfg->tile_h;
+    p->splat_lo[c] = so[s];
+    p->splat_hi[c] = so[s + 1];
+    p->pair_off[c + 1] = p->pair_off[c] + (so[s + 1] - so[s]);
+    p->tile_off[c + 1] = p->tile_off[c] + (int64_t)p->GX[c] * p->GY[c];
+    p->pix_off[c + 1] = p->pix_off[c] + (int64_t)w * h;
+    p->max_scene = std::max<int64_t>(p->max_scene, so[s + 1] - so[s]);
+  }
+  p->M = p->pair_off[p->C];
+  p->T = p->tile_off[p->C];
+  p->P = p->pix_off[p->C];
+  if (p->M >= 0xFFFFFFFFll) return fail(LS_ERR_UNSUPPORTED, "more than 2^32-1 (camera, splat) pairs");
+  if (p->T >= 0xFFFFFFFFll) return fail(LS_ERR_UNSUPPORTED, "more than 2^32-1 tiles");
+  int bits = 0;
+  while (bits < 32 && ((p->T - 1) >> bits) > 0) ++bits;
+  p->tile_bits = bits;
+
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  ls_layout& L = p->lay;
+  memset(&L, 0, sizeof(L));
+  L.n_pairs = p->M; L.n_tiles = p->T; L.n_pixels = p->P; L.capacity = cap;
+  const size_t M = (size_t)p->M, T = (size_t)p->T, CAP = (size_t)cap;
+  L.cams = take(sizeof(CamInfo) * p->C);
+  L.proj = take(sizeof(ProjRec) * M);
+  L.rect = take(8 * M);
+  L.ntiles = take(4 * M);
+  L.depth_key = take(4 * M);
+  L.order = take(4 * M);
+  L.isect_off = take(8 * (M + 1));
+  L.keys = take(4 * CAP);
+  L.vals = take(4 * CAP);
+  L.ranges = take(8 * (T + 1));
+  L.n_isect = take(8);
+  L.grad2d = take(4 * kGrad2d * M);
+  L.scratch = off;
+  p->flags = take(64);
+  p->pre_keys_a = take(4 * M);
+  p->pre_keys_b = take(4 * M);
+  p->pre_vals_a = take(4 * M);
+  p->pre_vals_b = take(4 * M);
+  p->sort_keys_b = take(4 * CAP);
+  p->sort_vals_b = take(4 * CAP);
+  auto blocks_for = [](int64_t n) {
+    int64_t tiles = (n + kSortTile - 1) / kSortTile;
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxSortBlocks));
+  };
+  p->sort_blocks = blocks_for(cap);
+  p->pre_blocks = blocks_for(p->M);
+  int32_t hb = std::max(p->sort_blocks, p->pre_blocks);
+  p->hist = take(4 * 256 * (size_t)hb);
+  p->digit_tot = take(4 * 256);
+  int64_t sb = (p->M + 1 + kScanThreads * 16 - 1) / (kScanThreads * 16);
+  p->scan_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(sb, kMaxScanBlocks));
+  p->scan_part = take(8 * (size_t)(p->scan_blocks + 1));
+  L.total_bytes = off;
+  return LS_OK;
+}
+
+static ls_status check_ws(const Plan& p, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(LS_ERR_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256) return fail(LS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < p.lay.total_bytes)
+    return fail(LS_ERR_WORKSPACE, "workspace has %zu bytes, plan needs %zu", ws_bytes,
+                p.lay.total_bytes);
+  return LS_OK;
+}
+
+static ls_status check_splats(const ls_config* cfg, const Plan& p, const ls_splats* sp) {
+  if (!sp) return fail(LS_ERR_INVALID_ARG, "splats is NULL");
+  if (sp->n != p.N)
+    return fail(LS_ERR_INVALID_ARG, "splats.n = %lld but scene offsets end at %lld",
+                (long long)sp->n, (long long)p.N);
+  if (p.N > 0 && (!sp->means || !sp->scales || !sp->quats || !sp->opacity || !sp->sh))
+    return fail(LS_ERR_INVALID_ARG, "splat attribute pointer is NULL");
+  (void)cfg;
+  return LS_OK;
+}
+
+}  // namespace lsplat
+
+using namespace lsplat;
+
+extern "C" {
+
+int ls_version(void) { return LSPLAT_VERSION; }
+
+const char* ls_last_error(void) { return g_err; }
+
+ls_status ls_workspace_size(const ls_config* cfg, const ls_cameras* cams, int64_t cap,
+                            size_t* bytes) {
+  if (!bytes) return fail(LS_ERR_INVALID_ARG, "bytes is NULL");
+  Plan p;
+  ls_status st = make_plan(cfg, cams, cap, &p);
+  if (st != LS_OK) return st;
+  *bytes = p.lay.total_bytes;
+  return LS_OK;
+}
+
+ls_status ls_workspace_layout(const ls_config* cfg, const ls_cameras* cams, int64_t cap,
+                              ls_layout* out) {
+  if (!out) return fail(LS_ERR_INVALID_ARG, "out is NULL");
+  Plan p;
+  ls_status st = make_plan(cfg, cams, cap, &p);
+  if (st != LS_OK) return st;
+  *out = p.lay;
+  return LS_OK;
+}
+
+ls_status ls_project(const ls_config* cfg, const ls_splats* sp, const ls_cameras* cams, void* ws,
+                     size_t ws_bytes, int64_t cap, void* stream) {
+  Plan p;
+  ls_status st = make_plan(cfg, cams, cap, &p);
+  if (st != LS_OK) return st;
+  if ((st = check_ws(p, ws, ws_bytes)) != LS_OK) return st;
+  if ((st = check_splats(cfg, p, sp)) != LS_OK) return st;
+  if (!cams->viewmat || !cams->intrin) return fail(LS_ERR_INVALID_ARG, "viewmat/intrin is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_cam_setup(p, cams, (char*)ws, s);
+  if (e != hipSuccess) return hip_fail(e, "cam_setup");
+  e = launch_project(p, cfg, sp, (char*)ws, s);
+  if (e != hipSuccess) return hip_fail(e, "project");
+  return LS_OK;
+}
+
+ls_status ls_bin_sort(const ls_config* cfg, const ls_cameras* cams, void* ws, size_t ws_bytes,
+                      int64_t cap, void* stream) {
+  Plan p;
+  ls_status st = make_plan(cfg, cams, cap, &p);
+  if (st != LS_OK) return st;
+  if ((st = check_ws(p, ws, ws_bytes)) != LS_OK) return st;
+  hipError_t e = launch_bin_sort(p, cfg, (char*)ws, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bin_sort");
+  return LS_OK;
+}
+
+ls_status ls_rasterize_fwd(const ls_config* cfg, const ls_cameras* cams, void* ws,
+                           size_t ws_bytes, int64_t cap, float* image, float* final_T,
+                           int32_t* last, void* stream) {
+  Plan p;
+  ls_status st = make_plan(cfg, cams, cap, &p);
+  if (st != LS_OK) return st;
+  if ((st = check_ws(p, ws, ws_bytes)) != LS_OK) return st;
+  if (!image || !final_T || !last) return fail(LS_ERR_INVALID_ARG, "image/final_T/last is NULL");
+  hipError_t e = launch_raster_fwd(p, cfg, (char*)ws, image, final_T, last, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rasterize_fwd");
+  return LS_OK;
+}
+
+ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* sp, const ls_cameras* cams,
+                           void* ws, size_t ws_bytes, int64_t cap, const float* final_T,
+                           const int32_t* last, const float* dL_dimage, const ls_grads* g,
+                           void* stream) {
+  Plan p;
+  ls_status st = make_plan(cfg, cams, cap, &p);
+  if (st != LS_OK) return st;
+  if ((st = check_ws(p, ws, ws_bytes)) != LS_OK) return st;
+  if ((st = check_splats(cfg, p, sp)) != LS_OK) return st;
+  if (!final_T || !last || !dL_dimage) return fail(LS_ERR_INVALID_ARG, "final_T/last/dL_dimage is NULL");
+  if (!g || (p.N > 0 && (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh)))
+    return fail(LS_ERR_INVALID_ARG, "gradient pointer is NULL");
+  hipError_t e = launch_raster_bwd(p, cfg, sp, (char*)ws, final_T, last, dL_dimage, g,
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rasterize_bwd");
+  return LS_OK;
+}
+
+}  // extern "C"

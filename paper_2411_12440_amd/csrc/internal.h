@@ -1,0 +1,110 @@
+// Internal declarations shared by the HIP translation units of liblsplat.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lsplat.h"
+
+namespace lsplat {
+
+// ---------------------------------------------------------------------------
+// Device-side camera record, written into the workspace by the projection
+// call.  Double copies of the matrices feed the FP64 geometry, float copies
+// feed the FP32 binning sequence.
+// ---------------------------------------------------------------------------
+struct alignas(16) CamInfo {
+  double R[9];          // world->camera rotation, row-major
+  double t[3];          // translation
+  double campos[3];     // camera centre in world space, -R^T t
+  double fx, fy, cx, cy;
+  float vm32[12];       // FP32 viewmat as given
+  float in32[4];        // FP32 (fx, fy, cx, cy) as given
+  int64_t pair_off;     // first pair index of this camera
+  int64_t tile_off;     // first global tile id
+  int64_t pix_off;      // first pixel index
+  int64_t splat_lo;     // first splat of the camera's scene
+  int64_t splat_hi;     // one past the last
+  int32_t W, H, GX, GY;
+  int32_t scene;
+  int32_t pad[3];
+};
+
+// 64-byte projected record (gathered per tile by the raster kernels).
+struct alignas(16) ProjRec {
+  double mx, my;        // projected centre (FP64)
+  double A, B, C;       // conic: D'^2 = A dx^2 + 2 B dx dy + C dy^2
+  float r, g, b;        // colour
+  float o;              // opacity
+  float pad0, pad1;
+};
+static_assert(sizeof(ProjRec) == 64, "ProjRec must be 64 bytes");
+
+constexpr int kGrad2d = 9;   // per-pair 2D gradient sums, see raster.hip
+
+// Launch plan derived on the host from the settings and the cameras.
+struct Plan {
+  int32_t C = 0, S = 0;
+  int64_t N = 0;          // splats
+  int64_t M = 0;          // (camera, splat) pairs
+  int64_t T = 0;          // tiles
+  int64_t P = 0;          // pixels
+  int64_t cap = 0;        // intersection capacity
+  int32_t tile_bits = 0;  // bits of the largest global tile id
+  int32_t max_scene = 0;  // largest scene size (splats)
+  std::vector<int32_t> W, H, GX, GY, scene;
+  std::vector<int64_t> pair_off, tile_off, pix_off, splat_lo, splat_hi;
+  ls_layout lay{};
+  // scratch sub-allocations (byte offsets from the workspace base)
+  size_t sort_keys_b = 0, sort_vals_b = 0, pre_keys_a = 0, pre_keys_b = 0, pre_vals_a = 0, pre_vals_b = 0,
+         hist = 0, digit_tot = 0, scan_part = 0, flags = 0;
+  int32_t sort_blocks = 0;    // radix sort grid for the intersection sort
+  int32_t pre_blocks = 0;     // radix sort grid for the depth presort
+  int32_t scan_blocks = 0;
+};
+
+// Radix sort geometry: 256 threads, 16 keys per thread per tile.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kMaxSortBlocks = 1024;
+constexpr int kScanThreads = 256;
+constexpr int kMaxScanBlocks = 1024;
+
+// ---------------------------------------------------------------------------
+// wave64 sum with DPP (gfx9 row rotations, then row broadcasts).  Every lane
+// passes its value; the full sum is returned in all lanes of row 3 (lanes
+// 48..63); read it with __builtin_amdgcn_readlane(x, 63).
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x += dpp_move<0x128>(x);        // row_ror:8
+  x += dpp_move<0x124>(x);        // row_ror:4
+  x += dpp_move<0x122>(x);        // row_ror:2
+  x += dpp_move<0x121>(x);        // row_ror:1  -> every lane holds its row sum
+  x += dpp_move<0x142, 0xA>(x);   // row_bcast:15 -> rows 1, 3 add rows 0, 2
+  x += dpp_move<0x143, 0xC>(x);   // row_bcast:31 -> rows 2, 3 add lane 31
+  return x;
+}
+
+// host launchers (each returns hipSuccess or the launch error)
+hipError_t launch_cam_setup(const Plan& p, const ls_cameras* cams, char* ws, hipStream_t s);
+hipError_t launch_project(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
+                          hipStream_t s);
+hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStream_t s);
+hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, float* image,
+                             float* final_T, int32_t* last, hipStream_t s);
+hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
+                              const ls_grads* g, hipStream_t s);
+hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
+                             const float* final_T, const int32_t* last, const float* dL_dimage,
+                             const ls_grads* g, hipStream_t s);
+
+}  // namespace lsplat

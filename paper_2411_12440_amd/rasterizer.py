@@ -1,0 +1,142 @@
+"""PyTorch-facing wrapper around liblsplat.
+
+PyTorch supplies device memory (the workspace and the outputs are torch
+tensors) and the stream; every stage runs in the library's HIP kernels through
+the ctypes binding.  Splat attributes use the library's planar layout:
+means/scales [3, N], quats [4, N], opacity [N], sh [K, 3, N] (float32, cuda).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def scene_to_device(scene, device="cuda"):
+    """numpy Scene ([N, d] arrays) -> dict of planar float32 device tensors."""
+    def planar(a):
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32).T)).to(device)
+    sh = np.asarray(scene.sh, np.float32)                       # [N, K, 3]
+    return dict(means=planar(scene.means), scales=planar(scene.scales), quats=planar(scene.quats),
+                opacity=torch.from_numpy(np.ascontiguousarray(scene.opacity, np.float32)).to(device),
+                sh=torch.from_numpy(np.ascontiguousarray(sh.transpose(1, 2, 0))).to(device))
+
+
+class Rasterizer:
+    """Holds the camera set, the settings and a workspace sized for an
+    intersection capacity.
+
+    ``forward`` runs project -> bin_sort -> rasterize_fwd.  With
+    ``check_capacity`` (default) it reads the intersection count back after
+    binning and, if the workspace is too small, grows it and bins again;
+    without it nothing synchronises and an overflow leaves an empty composite
+    (``overflowed()`` tells).
+    """
+
+    def __init__(self, cams, scene_splat_off, device="cuda", capacity=None, **cfg):
+        self.device = torch.device(device)
+        self.cfg = B.make_config(**cfg)
+        self.cams_np = cams
+        vm = torch.from_numpy(np.ascontiguousarray(cams.viewmat, np.float32)).to(self.device)
+        it = torch.from_numpy(np.ascontiguousarray(cams.intrin, np.float32)).to(self.device)
+        self.cams = B.CamerasHost(vm, it, cams.width, cams.height, cams.scene_of_cam,
+                                  scene_splat_off)
+        self.capacity = 0
+        self.ws = None
+        self.layout = None
+        self.image = self.final_T = self.last = None
+        self._alloc(int(capacity) if capacity is not None else 1 << 20)
+
+    # -- memory ---------------------------------------------------------------
+    def _alloc(self, capacity: int):
+        nbytes = B.ls_workspace_size(self.cfg, self.cams, capacity)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.capacity = capacity
+        self.layout = B.ls_workspace_layout(self.cfg, self.cams, capacity)
+        P = int(self.layout.n_pixels)
+        if self.image is None:
+            self.image = torch.empty(3 * P, dtype=torch.float32, device=self.device)
+            self.final_T = torch.empty(P, dtype=torch.float32, device=self.device)
+            self.last = torch.empty(P, dtype=torch.int32, device=self.device)
+
+    def view(self, name: str, dtype, count: int, offset_elems: int = 0) -> torch.Tensor:
+        """Typed view of one workspace array (see ls_layout)."""
+        off = getattr(self.layout, name)
+        esz = torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off + offset_elems * esz: off + (offset_elems + count) * esz].view(dtype)
+
+    def n_isect(self) -> int:
+        return int(self.view("n_isect", torch.int64, 1).item())
+
+    def overflowed(self) -> bool:
+        return self.n_isect() > self.capacity
+
+    # -- stages -----------------------------------------------------------------
+    def _splats(self, sp):
+        n = int(sp["opacity"].shape[0])
+        return B.splats_struct(n, sp["means"], sp["scales"], sp["quats"], sp["opacity"], sp["sh"])
+
+    def project(self, sp, stream=None):
+        B.ls_project(self.cfg, self._splats(sp), self.cams, self.ws, self.capacity,
+                     self._stream(stream))
+
+    def bin_sort(self, stream=None):
+        B.ls_bin_sort(self.cfg, self.cams, self.ws, self.capacity, self._stream(stream))
+
+    def rasterize_fwd(self, stream=None):
+        B.ls_rasterize_fwd(self.cfg, self.cams, self.ws, self.capacity, self.image,
+                           self.final_T, self.last, self._stream(stream))
+
+    def rasterize_bwd(self, sp, dL_dimage, grads, stream=None):
+        g = B.grads_struct(grads["means"], grads["scales"], grads["quats"], grads["opacity"],
+                           grads["sh"])
+        B.ls_rasterize_bwd(self.cfg, self._splats(sp), self.cams, self.ws, self.capacity,
+                           self.final_T, self.last, dL_dimage.contiguous(), g,
+                           self._stream(stream))
+
+    def _stream(self, stream):
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return stream.cuda_stream
+
+    # -- composite calls ---------------------------------------------------------
+    def forward(self, sp, check_capacity=True, stream=None):
+        self.project(sp, stream)
+        self.bin_sort(stream)
+        if check_capacity:
+            n = self.n_isect()
+            if n > self.capacity:
+                self._alloc(int(n * 1.25) + 1024)
+                self.project(sp, stream)
+                self.bin_sort(stream)
+        self.rasterize_fwd(stream)
+        return self.image, self.final_T, self.last
+
+    def backward(self, sp, dL_dimage, stream=None):
+        grads = {k: torch.empty_like(v) for k, v in sp.items()}
+        self.rasterize_bwd(sp, dL_dimage, grads, stream)
+        return grads
+
+
+class RenderFunction(torch.autograd.Function):
+    """image = render(means, scales, quats, opacity, sh) through a Rasterizer;
+    the backward pass is the library's hand-written reverse pass."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacity, sh, rast: Rasterizer):
+        sp = dict(means=means.contiguous(), scales=scales.contiguous(), quats=quats.contiguous(),
+                  opacity=opacity.contiguous(), sh=sh.contiguous())
+        image, _, _ = rast.forward(sp)
+        ctx.rast = rast
+        ctx.sp = sp
+        return image.clone()
+
+    @staticmethod
+    def backward(ctx, dL_dimage):
+        g = ctx.rast.backward(ctx.sp, dL_dimage.contiguous())
+        return g["means"], g["scales"], g["quats"], g["opacity"], g["sh"], None
+
+
+def render(means, scales, quats, opacity, sh, rast: Rasterizer):
+    return RenderFunction.apply(means, scales, quats, opacity, sh, rast)

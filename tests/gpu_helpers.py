@@ -1,0 +1,187 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and the FP64 oracle on the same seeded inputs, and compare."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+from oracle import RasterConfig, render_backward, render_forward
+from oracle import binning as obin
+
+REL = 1e-5          # relative tolerance on colours and gradients (FP32 path)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cfg_pair(**kw):
+    """Matching oracle and library settings."""
+    kw = dict(kw)
+    strict = kw.pop("strict", False)
+    okw = dict(lambda_=kw.get("lambda_", 2.5), ags=kw.get("ags", False),
+               ags_arg=kw.get("ags_arg", 0), ags_scope=kw.get("ags_scope", 0),
+               tile_w=kw.get("tile_w", 16), tile_h=kw.get("tile_h", 16),
+               bg=kw.get("bg", (0.0, 0.0, 0.0)), clip=kw.get("clip", 1.3))
+    if strict:
+        okw.update(alpha_min=0.0, t_min=0.0)
+    ocfg = RasterConfig(**okw)
+    gkw = dict(lambda_=ocfg.lambda_, eps2d=ocfg.eps2d, alpha_min=ocfg.alpha_min,
+               alpha_max=ocfg.alpha_max, t_min=ocfg.t_min, near=ocfg.near, far=ocfg.far,
+               clip=ocfg.clip, bg=ocfg.bg, ags=ocfg.ags, ags_arg=ocfg.ags_arg,
+               ags_scope=ocfg.ags_scope, tile_w=ocfg.tile_w, tile_h=ocfg.tile_h,
+               batch=kw.get("batch", 0))
+    return ocfg, gkw
+
+
+def gpu_forward(scene, off, cams, gkw, capacity=None):
+    import torch
+    from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
+    sp = scene_to_device(scene)
+    rast = Rasterizer(cams, off, capacity=capacity, sh_degree=scene.sh_degree, **gkw)
+    rast.forward(sp)
+    torch.cuda.synchronize()
+    return rast, sp
+
+
+def gpu_arrays(rast):
+    """Pull the workspace arrays and outputs to numpy."""
+    import torch
+    L = rast.layout
+    M, T = int(L.n_pairs), int(L.n_tiles)
+    n = rast.n_isect()
+    proj = rast.view("proj", torch.uint8, 64 * M).cpu().numpy()
+    rec = proj.view(np.float64).reshape(M, 8)
+    recf = proj.view(np.float32).reshape(M, 16)
+    out = dict(
+        mean2d=rec[:, 0:2], conic=rec[:, 2:5], rgb=recf[:, 10:13], opac=recf[:, 13],
+        rect=rast.view("rect", torch.int16, 4 * M).cpu().numpy().view(np.uint16).reshape(M, 4).astype(np.int64),
+        ntiles=rast.view("ntiles", torch.int32, M).cpu().numpy().view(np.uint32).astype(np.int64),
+        depth_key=rast.view("depth_key", torch.int32, M).cpu().numpy().view(np.uint32),
+        order=rast.view("order", torch.int32, M).cpu().numpy().view(np.uint32),
+        n_isect=n,
+        ranges=rast.view("ranges", torch.int64, T + 1).cpu().numpy(),
+        image=rast.image.cpu().numpy().astype(np.float64),
+        final_T=rast.final_T.cpu().numpy().astype(np.float64),
+        last=rast.last.cpu().numpy().astype(np.int64),
+    )
+    nv = min(n, rast.capacity)
+    out["vals"] = rast.view("vals", torch.int32, nv).cpu().numpy().view(np.uint32).astype(np.int64)
+    out["keys"] = rast.view("keys", torch.int32, nv).cpu().numpy().view(np.uint32).astype(np.int64)
+    return out
+
+
+def rms(x):
+    x = np.asarray(x, np.float64).ravel()
+    return math.sqrt(float(np.mean(x * x))) if x.size else 0.0
+
+
+def assert_close(name, x, ref, rel=REL, mask=None):
+    """Normwise and RMS-floored elementwise relative error bound."""
+    x = np.asarray(x, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    if mask is not None:
+        m = np.asarray(mask).ravel()
+        x, ref = x[m], ref[m]
+    assert x.shape == ref.shape, (name, x.shape, ref.shape)
+    assert np.all(np.isfinite(x)), f"{name}: non-finite values"
+    if ref.size == 0:
+        return
+    nr = np.linalg.norm(ref)
+    err = np.abs(x - ref)
+    if nr > 0:
+        normwise = np.linalg.norm(x - ref) / nr
+    else:
+        normwise = float(np.linalg.norm(x - ref))
+    floor = rel * (np.abs(ref) + rms(ref))
+    worst = np.max(err / np.maximum(floor / rel, 1e-300))
+    say(f"  {name}: n={ref.size} normwise={normwise:.2e} worst_elem_ratio={worst:.2e}")
+    assert normwise <= rel, f"{name}: normwise error {normwise:.3e} > {rel}"
+    bad = err > floor
+    assert not bad.any(), (f"{name}: {bad.sum()} elements exceed the bound; worst at "
+                           f"{np.argmax(err - floor)}: got {x[np.argmax(err - floor)]!r} "
+                           f"want {ref[np.argmax(err - floor)]!r}")
+
+
+def pixel_flags_to_image(flag, cams):
+    """Expand per-pixel flags to the planar image layout."""
+    out = []
+    off = 0
+    for c in range(cams.n):
+        n = int(cams.width[c]) * int(cams.height[c])
+        f = flag[off:off + n]
+        out.append(np.concatenate([f, f, f]))
+        off += n
+    return np.concatenate(out)
+
+
+def compare_binning(g, fw):
+    """Bit-exact comparison of every integer the binning produces."""
+    vis = fw.ntiles > 0
+    np.testing.assert_array_equal(g["ntiles"], fw.ntiles)
+    np.testing.assert_array_equal(g["depth_key"][vis], fw.depth_key[vis])
+    assert np.all(g["depth_key"][~vis] == 0xFFFFFFFF)
+    np.testing.assert_array_equal(g["rect"][vis], fw.rect[vis])
+    assert g["n_isect"] == len(fw.sorted_ids) == int(fw.ntiles.sum())
+    np.testing.assert_array_equal(g["vals"], fw.sorted_ids)
+    np.testing.assert_array_equal(g["keys"], fw.sorted_gtile)
+    np.testing.assert_array_equal(g["ranges"], fw.ranges)
+    # the depth presort: a permutation sorted by (depth_key, pair id)
+    dk = g["depth_key"].astype(np.int64)
+    ref_order = np.lexsort((np.arange(len(dk)), dk))
+    np.testing.assert_array_equal(g["order"], ref_order)
+
+
+def compare_projection(g, fw):
+    vis = fw.ntiles > 0
+    mean2d = np.concatenate([p["mean2d"] for p in fw.proj])
+    conic = np.concatenate([p["conic"] for p in fw.proj])
+    rgb = np.concatenate([p["rgb"] for p in fw.proj])
+    np.testing.assert_allclose(g["mean2d"][vis], mean2d[vis], rtol=1e-12, atol=1e-9)
+    # conic: FP64 on both sides, different operation order
+    scale = np.abs(conic[vis]).max(axis=1, keepdims=True)
+    assert np.all(np.abs(g["conic"][vis] - conic[vis]) <= 1e-9 * scale)
+    np.testing.assert_allclose(g["rgb"][vis], rgb[vis], rtol=1e-6, atol=1e-7)
+
+
+def compare_forward(g, fw, cams, tiles_mask_pix=None):
+    flag = fw.flag.copy()
+    done = ~np.isnan(fw.final_T)
+    if tiles_mask_pix is not None:
+        done &= tiles_mask_pix
+    ok = done & ~flag
+    say(f"  pixels compared: {ok.sum()} (flagged near a threshold: {(done & flag).sum()})")
+    img_ok = pixel_flags_to_image(ok, cams)
+    assert_close("image", g["image"], fw.image, mask=img_ok)
+    assert_close("final_T", g["final_T"], fw.final_T, mask=ok)
+    np.testing.assert_array_equal(g["last"][ok], fw.last[ok])
+    # flagged pixels: a decision near a threshold may flip; bound the jump
+    fl = done & flag
+    if fl.any():
+        imf = pixel_flags_to_image(fl, cams)
+        assert np.max(np.abs(g["image"][imf] - fw.image[imf])) < 0.05
+    return ok
+
+
+def oracle_grads_masked(fw, scene, cams, G):
+    return render_backward(fw, scene, cams, G)
+
+
+def compare_grads(grads_gpu, go, scene, rel=REL):
+    """grads_gpu: dict of planar numpy arrays from the library."""
+    N = scene.n
+    K = scene.sh.shape[1]
+    assert_close("d_means", grads_gpu["means"].T, go["means"], rel)
+    assert_close("d_scales", grads_gpu["scales"].T, go["scales"], rel)
+    assert_close("d_quats", grads_gpu["quats"].T, go["quats"], rel)
+    assert_close("d_opacity", grads_gpu["opacity"], go["opacity"], rel)
+    assert_close("d_sh", grads_gpu["sh"].reshape(K, 3, N).transpose(2, 0, 1), go["sh"], rel)
+
+
+def tile_list_oracle(fw, gtile):
+    """Plain definition of one tile's list: the pairs whose rect contains the
+    tile, ordered by (depth key, pair id)."""
+    return obin.tile_list(fw.rect, fw.ntiles, fw.depth_key, gtile, fw.lay)

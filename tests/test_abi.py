@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every entry point that include/lsplat.h
+declares, and validates arguments on the host.  No kernel is launched."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsplat.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ls_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd",
+              "ls_workspace_size", "ls_workspace_layout", "ls_last_error", "ls_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2411_12440_amd import binding as B
+    lib = C.CDLL(B.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(B.EXPORTS) == set(declared_functions())
+    assert B.ls_version() == 100
+
+
+def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):
+    from paper_2411_12440_amd import binding as B
+    return B.CamerasHost(None, None, np.array(w), np.array(h), np.array(scene), np.array(off))
+
+
+def test_workspace_size_and_layout():
+    from paper_2411_12440_amd import binding as B
+    cfg = B.make_config()
+    cams = _cams(w=(128, 40), h=(128, 24), scene=(0, 0), off=(0, 1000))
+    s0 = B.ls_workspace_size(cfg, cams, 0)
+    s1 = B.ls_workspace_size(cfg, cams, 1 << 20)
+    s2 = B.ls_workspace_size(cfg, cams, 1 << 21)
+    assert 0 < s0 < s1 < s2
+    lay = B.ls_workspace_layout(cfg, cams, 1 << 20)
+    assert lay.n_pairs == 2000
+    assert lay.n_tiles == 64 + 3 * 2
+    assert lay.n_pixels == 128 * 128 + 40 * 24
+    assert lay.total_bytes == s1
+    offs = [lay.cams, lay.proj, lay.rect, lay.ntiles, lay.depth_key, lay.order, lay.isect_off,
+            lay.keys, lay.vals, lay.ranges, lay.n_isect, lay.grad2d, lay.scratch]
+    assert all(o % 256 == 0 for o in offs)
+    assert offs == sorted(offs)
+    assert lay.vals - lay.keys >= 4 * (1 << 20)
+
+
+@pytest.mark.parametrize("field,value", [("lambda_", 0.0), ("eps2d", 0.0), ("alpha_max", 1.0),
+                                         ("t_min", -1.0), ("sh_degree", 4), ("ags", 2),
+                                         ("batch", 100), ("near_z", -1.0)])
+def test_invalid_config_rejected(field, value):
+    from paper_2411_12440_amd import binding as B
+    cfg = B.make_config()
+    setattr(cfg, field, value)
+    with pytest.raises(B.LsError) as ei:
+        B.ls_workspace_size(cfg, _cams(), 0)
+    assert ei.value.status in (-1, -4)
+    assert len(B.LIB.ls_last_error()) > 0
+
+
+def test_invalid_cameras_rejected():
+    from paper_2411_12440_amd import binding as B
+    cfg = B.make_config()
+    for kw in (dict(w=(0,)), dict(h=(20000,)), dict(scene=(1,)), dict(off=(1, 10))):
+        with pytest.raises(B.LsError):
+            B.ls_workspace_size(cfg, _cams(**kw), 0)
+    cfg.tile_w, cfg.tile_h = 12, 12
+    with pytest.raises(B.LsError) as ei:
+        B.ls_workspace_size(cfg, _cams(), 0)
+    assert ei.value.status == -4
+
+
+def test_null_workspace_and_buffers_rejected():
+    """Entry points validate pointers before launching anything."""
+    from paper_2411_12440_amd import binding as B
+    cfg = B.make_config()
+    cams = _cams()
+    lib = B.LIB
+    st = lib.ls_bin_sort(C.byref(cfg), C.byref(cams.c), None, 0, 0, None)
+    assert st == -5
+    sp = B.Splats(10, 0, 0, 0, 0, 0)
+    st = lib.ls_project(C.byref(cfg), C.byref(sp), C.byref(cams.c), None, 0, 0, None)
+    assert st == -5
+    st = lib.ls_rasterize_fwd(C.byref(cfg), C.byref(cams.c), None, 0, 0, None, None, None, None)
+    assert st == -5
+    # splat count must match the scene offsets (checked before any launch)
+    ws = C.create_string_buffer(B.ls_workspace_size(cfg, cams, 0) + 256)
+    base = (C.addressof(ws) + 255) // 256 * 256
+    sp = B.Splats(11, 1, 1, 1, 1, 1)
+    st = lib.ls_project(C.byref(cfg), C.byref(sp), C.byref(cams.c), base, len(ws.raw) - 256, 0, None)
+    assert st == -1
+    assert b"splats.n" in lib.ls_last_error()

@@ -1,0 +1,209 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Integers bit-exact; colours and gradients within 1e-5
+relative (normwise and RMS-floored per element); pixels whose skip/stop
+decision lies within 1e-4 of a threshold are excluded from the element check
+and bounded separately."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import render_backward, render_forward
+from paper_2411_12440_amd import scenes
+from tests.gpu_helpers import (assert_close, cfg_pair, compare_binning, compare_forward,
+                               compare_grads, compare_projection, gpu_arrays, gpu_forward,
+                               pixel_flags_to_image, say)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _grads_to_numpy(g):
+    return {k: v.detach().cpu().numpy().astype(np.float64) for k, v in g.items()}
+
+
+def _run_fwd_bwd(scene, off, cams, gkw, G):
+    import torch
+    rast, sp = gpu_forward(scene, off, cams, gkw)
+    g = gpu_arrays(rast)
+    grads = rast.backward(sp, torch.from_numpy(G.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    return g, _grads_to_numpy(grads)
+
+
+def test_workload1_forward():
+    say("case: workload 1 (1k splats, SH0, 128x128) forward")
+    scene, off, cams = scenes.workload(1)
+    ocfg, gkw = cfg_pair()
+    rast, _ = gpu_forward(scene, off, cams, gkw)
+    g = gpu_arrays(rast)
+    fw = render_forward(scene, off, cams, ocfg)
+    compare_binning(g, fw)
+    compare_projection(g, fw)
+    compare_forward(g, fw, cams)
+
+
+@pytest.mark.parametrize("tw,th,batch", [(16, 16, 0), (16, 8, 64), (8, 8, 0), (32, 8, 128)])
+def test_ragged_tile_shapes(tw, th, batch):
+    say(f"case: ragged 150x100, tile {tw}x{th}, batch {batch}")
+    scene = scenes.make_scene(1500, 4242, -3.0, 0.5, 1)
+    cams = scenes.front_camera(150, 100)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair(tile_w=tw, tile_h=th, batch=batch)
+    rast, _ = gpu_forward(scene, off, cams, gkw)
+    g = gpu_arrays(rast)
+    fw = render_forward(scene, off, cams, ocfg)
+    compare_binning(g, fw)
+    compare_forward(g, fw, cams)
+
+
+@pytest.mark.parametrize("ags,ags_arg,ags_scope,strict", [(False, 0, 0, False), (True, 0, 0, False),
+                                                         (True, 1, 0, True), (True, 0, 1, False),
+                                                         (False, 0, 0, True)])
+def test_forward_backward_small(ags, ags_arg, ags_scope, strict):
+    say(f"case: fwd+bwd 3000 splats SH3 200x120 ags={ags} arg={ags_arg} scope={ags_scope} strict={strict}")
+    scene = scenes.make_scene(3000, 77, -3.0, 0.5, 3)
+    cams = scenes.front_camera(200, 120)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair(ags=ags, ags_arg=ags_arg, ags_scope=ags_scope, strict=strict,
+                         bg=(0.1, 0.2, 0.3))
+    G = scenes.upstream_grad(cams, 7002)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    # zero the upstream gradient where a decision sits on a threshold
+    G = G * ~pixel_flags_to_image(fw.flag, cams)
+    g, grads = _run_fwd_bwd(scene, off, cams, gkw, G)
+    compare_binning(g, fw)
+    compare_forward(g, fw, cams)
+    go = render_backward(fw, scene, cams, G)
+    compare_grads(grads, go, scene)
+
+
+def test_multi_camera_multi_scene():
+    say("case: 3 scenes, 6 cameras of uneven size, fwd+bwd")
+    scs = [scenes.make_scene(n, 900 + i, -3.0, 0.5, 2) for i, n in enumerate((700, 1200, 400))]
+    scene, off = scenes.concat_scenes(scs)
+    res = [(96, 64), (130, 70), (64, 64), (200, 90), (50, 120), (128, 96)]
+    cams = scenes.sphere_cameras(6, 4.0, res, scene_of_cam=[0, 1, 2, 0, 1, 2])
+    ocfg, gkw = cfg_pair()
+    G = scenes.upstream_grad(cams, 7003)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    G = G * ~pixel_flags_to_image(fw.flag, cams)
+    g, grads = _run_fwd_bwd(scene, off, cams, gkw, G)
+    compare_binning(g, fw)
+    compare_projection(g, fw)
+    compare_forward(g, fw, cams)
+    go = render_backward(fw, scene, cams, G)
+    compare_grads(grads, go, scene)
+
+
+def test_workload2_binning_and_sampled_tiles():
+    """100k splats, SH3, 1280x720: full binning bit-exact; composite and
+    gradients compared on a seeded sample of tiles (upstream gradient zero
+    elsewhere)."""
+    say("case: workload 2 (100k splats, SH3, 1280x720)")
+    scene, off, cams = scenes.workload(2)
+    ocfg, gkw = cfg_pair(ags=True)
+    rng = np.random.default_rng(11)
+    T = 80 * 45
+    tiles = np.sort(rng.choice(T, 40, replace=False))
+    fw = render_forward(scene, off, cams, ocfg, tiles=tiles, want_pairs=True)
+    G = scenes.upstream_grad(cams, 7002)
+    ok = ~np.isnan(fw.final_T) & ~fw.flag
+    G = G * pixel_flags_to_image(ok, cams)
+    g, grads = _run_fwd_bwd(scene, off, cams, gkw, G)
+    compare_binning(g, fw)
+    compare_projection(g, fw)
+    compare_forward(g, fw, cams)
+    go = render_backward(fw, scene, cams, G)
+    compare_grads(grads, go, scene)
+
+
+def test_empty_and_culled():
+    import torch
+    say("case: every splat behind the camera; and an empty scene")
+    scene = scenes.make_scene(500, 5, -3.0, 0.5, 0)
+    scene.means[:, 2] = -5.0            # behind the camera at z = -3
+    cams = scenes.front_camera(64, 48)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair(bg=(0.25, 0.5, 0.75))
+    rast, _ = gpu_forward(scene, off, cams, gkw)
+    g = gpu_arrays(rast)
+    assert g["n_isect"] == 0 and np.all(g["ntiles"] == 0)
+    img = g["image"].reshape(3, -1)
+    np.testing.assert_array_equal(img[0], 0.25)
+    np.testing.assert_array_equal(img[2], 0.75)
+    assert np.all(g["final_T"] == 1.0) and np.all(g["last"] == 0)
+    empty = scenes.Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32),
+                         np.zeros((0, 4), np.float32), np.zeros(0, np.float32),
+                         np.zeros((0, 1, 3), np.float32), 0)
+    rast, sp = gpu_forward(empty, np.array([0, 0]), cams, gkw)
+    g = gpu_arrays(rast)
+    assert g["n_isect"] == 0
+    np.testing.assert_array_equal(g["image"].reshape(3, -1)[1], 0.5)
+    grads = rast.backward(sp, torch.ones(3 * 64 * 48, device="cuda"))
+    torch.cuda.synchronize()
+
+
+def test_capacity_overflow_is_reported():
+    say("case: intersection capacity too small")
+    import torch
+    from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
+    scene, off, cams = scenes.workload(1)
+    ocfg, gkw = cfg_pair(bg=(0.5, 0.5, 0.5))
+    rast = Rasterizer(cams, off, capacity=100, sh_degree=0, **gkw)
+    sp = scene_to_device(scene)
+    rast.forward(sp, check_capacity=False)
+    torch.cuda.synchronize()
+    fw = render_forward(scene, off, cams, ocfg, tiles=[])
+    assert rast.n_isect() == len(fw.sorted_ids) > 100
+    assert rast.overflowed()
+    assert torch.all(rast.image == 0.5)
+    # growing the capacity recovers the exact result
+    rast.forward(sp, check_capacity=True)
+    torch.cuda.synchronize()
+    g = gpu_arrays(rast)
+    compare_binning(g, fw)
+
+
+def test_fullscreen_splats():
+    """A few splats larger than the image (every tile) among small ones; the
+    keygen load balancing must give every tile its entry."""
+    say("case: full-screen splats")
+    scene = scenes.make_scene(800, 31, -3.0, 0.5, 0)
+    scene.scales[:5] = 3.0
+    cams = scenes.front_camera(160, 96)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair()
+    rast, _ = gpu_forward(scene, off, cams, gkw)
+    g = gpu_arrays(rast)
+    fw = render_forward(scene, off, cams, ocfg)
+    assert fw.ntiles[:5].min() == 60
+    compare_binning(g, fw)
+    compare_forward(g, fw, cams)
+
+
+def test_autograd_function():
+    import torch
+    from paper_2411_12440_amd.rasterizer import Rasterizer, render, scene_to_device
+    say("case: torch.autograd.Function")
+    scene = scenes.make_scene(1000, 8, -3.0, 0.5, 1)
+    cams = scenes.front_camera(96, 80)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair(strict=True)
+    sp = scene_to_device(scene)
+    rast = Rasterizer(cams, off, sh_degree=1, **gkw)
+    leaves = [sp[k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+    img = render(*leaves, rast)
+    G = scenes.upstream_grad(cams, 7010)
+    (img * torch.from_numpy(G).cuda()).sum().backward()
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    go = render_backward(fw, scene, cams, G)
+    got = {k: l.grad.detach().cpu().numpy().astype(np.float64)
+           for k, l in zip(("means", "scales", "quats", "opacity", "sh"), leaves)}
+    compare_grads(got, go, scene)
