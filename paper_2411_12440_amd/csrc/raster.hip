@@ -31,17 +31,18 @@ namespace {
 
 struct RasterParams {
   double lam2;        // lambda^2: D' >= lambda <=> outside the support
-  float inv_lam;
-  float amin, amax, oma_max, tmin;
+  double inv_lam;     // 1 / lambda
+  double amin, amax, oma_max, tmin;
   float bg0, bg1, bg2;
+  float inv_lam_f;
   int ags, ags_arg, ags_scope;
 };
 
-// alpha and 1 - alpha of one (pixel, splat) pair.  Shared by the forward and
-// backward kernels and evaluated without contraction and with explicit fused
-// operations, so both kernels take every skip/stop decision identically.
+// alpha and 1 - alpha of one (pixel, splat) pair, in FP64.  Shared by the
+// forward and backward kernels and evaluated without contraction, so both
+// kernels take every skip/stop decision identically.
 struct PairEval {
-  float D, alpha, oma;
+  double D, alpha, oma;
   bool clamped;
 };
 
@@ -49,13 +50,13 @@ __device__ __forceinline__ double quad_form(double dx, double dy, double A, doub
   return fma(dx, fma(A, dx, B2 * dy), (C * dy) * dy);
 }
 
-__device__ __forceinline__ PairEval pair_eval(double q, float o, const RasterParams& rp) {
+__device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterParams& rp) {
 #pragma clang fp contract(off)
   PairEval e;
-  e.D = __builtin_amdgcn_sqrtf((float)q);
-  const float t = o * (e.D * rp.inv_lam);
+  e.D = sqrt(q);
+  const double t = o * (e.D * rp.inv_lam);
   e.alpha = o - t;
-  e.oma = (1.f - o) + t;
+  e.oma = (1.0 - o) + t;
   e.clamped = e.alpha > rp.amax;
   if (e.clamped) {
     e.alpha = rp.amax;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   const double lxd = (double)lx, lyd = (double)ly;
   const int64_t start = ranges[tile], end = ranges[tile + 1];
 
-  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
+  double T = 1.0, cr = 0.0, cg = 0.0, cb = 0.0;
   int32_t lastc = 0;
   bool done = !inside;
   for (int64_t b0 = start; b0 < end; b0 += batch) {
@@ -139,18 +140,17 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
         const double dy = lyd - st.oy[j];
         const double q = quad_form(dx, dy, st.A[j], st.B2[j], st.C[j]);
         if (!(q < rp.lam2)) continue;
-        const PairEval e = pair_eval(q, st.o[j], rp);
-        const float alpha = e.alpha;
-        if (!(alpha > 0.f) || alpha < rp.amin) continue;
-        const float Tn = T * e.oma;
+        const PairEval e = pair_eval(q, (double)st.o[j], rp);
+        if (!(e.alpha > 0.0) || e.alpha < rp.amin) continue;
+        const double Tn = T * e.oma;
         if (Tn < rp.tmin) {
           done = true;
           break;
         }
-        const float w = alpha * T;
-        cr += st.r[j] * w;
-        cg += st.g[j] * w;
-        cb += st.b[j] * w;
+        const double w = e.alpha * T;
+        cr = fma((double)st.r[j], w, cr);
+        cg = fma((double)st.g[j], w, cg);
+        cb = fma((double)st.b[j], w, cb);
         T = Tn;
         lastc = (int32_t)(b0 - start) + j + 1;
       }
@@ -160,10 +160,10 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
     const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
     const int64_t plane = (int64_t)ci.W * ci.H;
     const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
-    image[ib] = cr + T * rp.bg0;
-    image[ib + plane] = cg + T * rp.bg1;
-    image[ib + 2 * plane] = cb + T * rp.bg2;
-    final_T[pix] = T;
+    image[ib] = (float)(cr + T * (double)rp.bg0);
+    image[ib + plane] = (float)(cg + T * (double)rp.bg1);
+    image[ib + 2 * plane] = (float)(cb + T * (double)rp.bg2);
+    final_T[pix] = (float)T;
     last[pix] = lastc;
   }
 }
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   const int64_t start = ranges[tile];
   const int64_t len = ranges[tile + 1] - start;
 
-  float T = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f;
+  double T = 1.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
   int32_t mylast = 0;
   if (inside) {
     const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
     G2 = dL_dimage[ib + 2 * plane];
   }
   // suffix colour behind the current splat, starting with the background term
-  float S0 = T * rp.bg0, S1 = T * rp.bg1, S2 = T * rp.bg2;
+  double S0 = T * (double)rp.bg0, S1 = T * (double)rp.bg1, S2 = T * (double)rp.bg2;
   // tile-wide maximum of `last`
   int32_t mx = mylast;
   for (int d = 32; d > 0; d >>= 1) {
@@ -245,53 +245,51 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
         const double A = st.A[jj], B2 = st.B2[jj], Cc = st.C[jj];
         const double q = quad_form(dx, dy, A, B2, Cc);
         if (q < rp.lam2) {
-          const PairEval e = pair_eval(q, st.o[jj], rp);
-          const float D = e.D, alpha = e.alpha, oma = e.oma;
-          const bool clamped = e.clamped;
-          const float o = st.o[jj];
-          const float Dl = D * rp.inv_lam;
-          if (alpha > 0.f && alpha >= rp.amin) {
+          const double o = (double)st.o[jj];
+          const PairEval e = pair_eval(q, o, rp);
+          if (e.alpha > 0.0 && e.alpha >= rp.amin) {
             contrib = true;
-            const float inv = __builtin_amdgcn_rcpf(oma);
-            const float Ti = T * inv;
-            const float w = alpha * Ti;
-            const float cr = st.r[jj], cg = st.g[jj], cb = st.b[jj];
-            gv[6] = w * G0;
-            gv[7] = w * G1;
-            gv[8] = w * G2;
-            const float GdC = G0 * cr + G1 * cg + G2 * cb;
-            const float GdS = G0 * S0 + G1 * S1 + G2 * S2;
-            const float dLda = Ti * GdC - GdS * inv;
-            S0 += cr * w;
-            S1 += cg * w;
-            S2 += cb * w;
+            const double inv = 1.0 / e.oma;
+            const double Ti = T * inv;
+            const double w = e.alpha * Ti;
+            const double cr = st.r[jj], cg = st.g[jj], cb = st.b[jj];
+            double g_r = w * G0, g_g = w * G1, g_b = w * G2;
+            const double GdC = G0 * cr + G1 * cg + G2 * cb;
+            const double GdS = G0 * S0 + G1 * S1 + G2 * S2;
+            const double dLda = Ti * GdC - GdS * inv;
+            S0 = fma(cr, w, S0);
+            S1 = fma(cg, w, S1);
+            S2 = fma(cb, w, S2);
             T = Ti;
-            float om = 1.f;
+            const double Dl = e.D * rp.inv_lam;
+            double om = 1.0;
             if (rp.ags) {
-              const float arg = rp.ags_arg ? Dl : D;
-              om = __expf(-arg * arg);
+              const float arg = (float)(rp.ags_arg ? Dl : e.D);
+              om = (double)__expf(-arg * arg);
             }
-            if (!clamped) {
-              const float Lp = 1.f - Dl;
-              gv[5] = Lp * dLda;
-              float dLdD = -(o * dLda) * rp.inv_lam * om;
-              if (D > 0.f) {
-                const float gq = 0.5f * dLdD / D;
-                const double gqd = (double)gq;
-                gv[0] = (float)(-2.0 * gqd * (A * dx + 0.5 * B2 * dy));
-                gv[1] = (float)(-2.0 * gqd * (0.5 * B2 * dx + Cc * dy));
-                const float fdx = (float)dx, fdy = (float)dy;
-                gv[2] = gq * fdx * fdx;
-                gv[3] = 2.f * gq * fdx * fdy;
-                gv[4] = gq * fdy * fdy;
+            double g_o = 0.0;
+            if (!e.clamped) {
+              g_o = (1.0 - Dl) * dLda;
+              const double dLdD = -(o * dLda) * rp.inv_lam * om;
+              if (e.D > 0.0) {
+                const double gq = 0.5 * dLdD / e.D;
+                gv[0] = (float)(-2.0 * gq * (A * dx + 0.5 * B2 * dy));
+                gv[1] = (float)(-2.0 * gq * (0.5 * B2 * dx + Cc * dy));
+                gv[2] = (float)(gq * dx * dx);
+                gv[3] = (float)(2.0 * gq * dx * dy);
+                gv[4] = (float)(gq * dy * dy);
               }
             }
             if (rp.ags_scope) {
-              gv[5] *= om;
-              gv[6] *= om;
-              gv[7] *= om;
-              gv[8] *= om;
+              g_o *= om;
+              g_r *= om;
+              g_g *= om;
+              g_b *= om;
             }
+            gv[5] = (float)g_o;
+            gv[6] = (float)g_r;
+            gv[7] = (float)g_g;
+            gv[8] = (float)g_b;
           }
         }
       }
@@ -324,10 +322,11 @@ __global__ void zero_kernel(float* __restrict__ p, int64_t n) {
 RasterParams make_params(const ls_config* cfg) {
   RasterParams rp;
   rp.lam2 = (double)cfg->lambda * (double)cfg->lambda;
-  rp.inv_lam = (float)(1.0 / (double)cfg->lambda);
+  rp.inv_lam = 1.0 / (double)cfg->lambda;
+  rp.inv_lam_f = (float)rp.inv_lam;
   rp.amin = cfg->alpha_min;
   rp.amax = cfg->alpha_max;
-  rp.oma_max = (float)(1.0 - (double)cfg->alpha_max);
+  rp.oma_max = 1.0 - (double)cfg->alpha_max;
   rp.tmin = cfg->t_min;
   rp.bg0 = cfg->bg[0];
   rp.bg1 = cfg->bg[1];
