@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Throughput of the linear-splat rasterizer, forward + backward, on one GPU.
+
+Workload (the paper-scale configuration): 3,200,000 splats with SH degree 3
+and log-normal scales N(-4, 1), rendered into 8 cameras of 1920x1080 on a
+sphere of radius 4 around the scene.  One step is the whole path over all
+8 views: projection, binning (presort, scan, key generation, tile sort,
+ranges), forward compositing, backward compositing and projection backward,
+with a seeded N(0, 1) upstream image gradient.
+
+Two paths are timed with the same kernels:
+  batched   all 8 views in one call sequence (one workspace, no host sync)
+  per-view  one view at a time, each with its own right-sized workspace and
+            a host read-back of the intersection count after binning
+The headline value is the batched rate.  The JSON line also carries the
+per-view rate, the dominant kernel's roofline fraction (kernel durations from
+HIP events recorded around every library launch during the timed region) and
+the FP64 oracle timed on a bounded sample on the host CPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VEC_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (FMA = 2 flops)
+METRIC = "Mpixel/s fwd+bwd, 3M linear splats @1080p: batched vs per-view"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--splats", type=int, default=3_200_000)
+    ap.add_argument("--ags", type=int, default=1)
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def make_workload(n_splats, views):
+    from paper_2411_12440_amd import scenes
+    scene = scenes.make_scene(n_splats, 1004, -4.0, 1.0, 3)
+    cams = scenes.sphere_cameras(views, 4.0, [(1920, 1080)] * views)
+    return scene, cams
+
+
+# --------------------------------------------------------------------------
+# algorithmic cost of each kernel per launch ("Roofline")
+# --------------------------------------------------------------------------
+
+def kernel_cost(name, w):
+    """(bound, amount per launch, unit) for the kernels we can price."""
+    N, M, n, K, Q = w["N"], w["M"], w["n_isect"], w["K"], w["Q"]
+    splat_bytes = 44 + 12 * K
+    if name == "tilesort_downsweep":
+        return "hbm", 16.0 * n, "B"
+    if name == "tilesort_upsweep":
+        return "hbm", 4.0 * n, "B"
+    if name == "presort_downsweep":
+        return "hbm", 16.0 * M, "B"
+    if name == "presort_upsweep":
+        return "hbm", 4.0 * M, "B"
+    if name == "keygen":
+        return "hbm", 8.0 * n + 20.0 * M, "B"
+    if name == "project":
+        return "hbm", float(splat_bytes) * N + 80.0 * M, "B"
+    if name == "project_bwd":
+        return "hbm", float(splat_bytes - 4) * N + 36.0 * M + float(splat_bytes) * N, "B"
+    if name in ("raster_fwd", "raster_bwd"):
+        # FP64 quadratic form of every (pixel, splat) pair up to the pixel's
+        # last contributor: 9 flops (2 sub, 3 mul, 2 fma)
+        return "alu", 9.0 * Q, "flop"
+    return None
+
+
+def source_hash(kernel):
+    fname = {"raster_fwd": "raster.hip", "raster_bwd": "raster.hip", "project": "project.hip",
+             "project_bwd": "project.hip"}.get(kernel, "binsort.hip")
+    with open(os.path.join(ROOT, "paper_2411_12440_amd", "csrc", fname), "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()[:12]
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha1") != source_hash(kernel):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# --------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample
+# --------------------------------------------------------------------------
+
+def cpu_baseline(scene, cams, n_tiles_sample=6):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import RasterConfig, binning, composite, projection
+    from oracle.render import layout
+    from paper_2411_12440_amd import scenes as S
+
+    cfg = RasterConfig(ags=True)
+    c = 0
+    W, H = int(cams.width[c]), int(cams.height[c])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        rect, nt, dk = binning.binning_fp32(scene.means, scene.scales, scene.quats, cams.viewmat[c],
+                                            cams.intrin[c], W, H, cfg)
+        p = projection.project(scene.means, scene.scales, scene.quats, scene.sh, scene.sh_degree,
+                               cams.viewmat[c], cams.intrin[c], W, H, cfg)
+        t_proj = time.perf_counter() - t0
+        one = cams.subset([c])
+        lay = layout(np.array([0, scene.n]), one, cfg)
+        gx, gy = lay.grid[0]
+        rng = np.random.default_rng(5)
+        tiles = rng.choice(gx * gy, n_tiles_sample, replace=False)
+        G = S.upstream_grad(one, 7004)
+        opac = scene.opacity.astype(np.float64)
+        t_tiles = 0.0
+        acc = [np.zeros((scene.n, 3)), np.zeros(scene.n), np.zeros((scene.n, 3)), np.zeros((scene.n, 2))]
+        for t in tiles:
+            t1 = time.perf_counter()
+            ids = binning.tile_list(rect, nt, dk, int(t), lay)
+            ty, tx = divmod(int(t), gx)
+            px, py = composite._tile_pixels(tx, ty, W, H, cfg)
+            res = composite.composite_tile(ids, px, py, p["mean2d"], p["conic"], opac, p["rgb"], cfg,
+                                           want_pairs=True)
+            Gt = np.stack([G[ch * W * H + py * W + px] for ch in range(3)], 1).astype(np.float64)
+            r = composite.reverse_tile(res, Gt, p["mean2d"], p["conic"], opac, p["rgb"], cfg, scene.n)
+            for a, b in zip(acc, r):
+                a += b
+            t_tiles += time.perf_counter() - t1
+        t1 = time.perf_counter()
+        projection.project_backward(p, scene.sh, scene.sh_degree, acc[3], acc[2], acc[0])
+        t_pbwd = time.perf_counter() - t1
+    per_view = t_proj + t_tiles / n_tiles_sample * (gx * gy) + t_pbwd
+    mpx = W * H / per_view / 1e6
+    sample = (f"one 1920x1080 view of the 3.2M-splat scene: projection + FP32 binning of all "
+              f"splats ({t_proj:.1f} s), forward+backward composite of {n_tiles_sample} random "
+              f"16x16 tiles ({t_tiles:.1f} s, scaled to all {gx * gy} tiles), projection backward "
+              f"of all splats ({t_pbwd:.1f} s); tile-list sort excluded; extrapolated")
+    return dict(value=round(mpx, 6), unit="Mpixel/s", cores=1, kind="oracle", sample=sample)
+
+
+# --------------------------------------------------------------------------
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this rasterizer runs on one GPU; multi-GPU runs are not part of this "
+              "build (see DESIGN.md for how the path would shard across GPUs).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2411_12440_amd import binding as B
+    from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
+    from paper_2411_12440_amd import scenes as S
+
+    dev = torch.device("cuda:0")
+    log(f"bench: building workload ({args.splats} splats, {args.views} views)")
+    scene, cams = make_workload(args.splats, args.views)
+    sp = scene_to_device(scene, dev)
+    G_all = torch.from_numpy(S.upstream_grad(cams, 7004)).to(dev)
+    cfgkw = dict(sh_degree=3, ags=bool(args.ags))
+    off = np.array([0, scene.n])
+    P = int(sum(int(w) * int(h) for w, h in zip(cams.width, cams.height)))
+
+    # ---- batched path -------------------------------------------------------
+    log("bench: sizing the batched workspace")
+    rast = Rasterizer(cams, off, device=dev, capacity=1 << 24, **cfgkw)
+    rast.forward(sp, check_capacity=True)
+    torch.cuda.synchronize()
+    n_isect = rast.n_isect()
+    if n_isect * 1.02 > rast.capacity:
+        rast._alloc(int(n_isect * 1.05) + 4096)
+    grads = {k: torch.empty_like(v) for k, v in sp.items()}
+
+    def step_batched():
+        rast.project(sp)
+        rast.bin_sort()
+        rast.rasterize_fwd()
+        rast.rasterize_bwd(sp, G_all, grads)
+
+    for _ in range(args.warmup):
+        step_batched()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} batched steps (n_isect={n_isect})")
+    B.ls_profile_read(reset=True)
+    B.ls_profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step_batched()
+    e1.record()
+    torch.cuda.synchronize()
+    B.ls_profile_enable(False)
+    ms_batched = e0.elapsed_time(e1) / args.steps
+    ktimes = B.ls_profile_read(reset=True)
+    assert not rast.overflowed()
+    last = rast.last.to(torch.int64)
+    Q = int(last.sum().item())
+    value = P / (ms_batched * 1e-3) / 1e6
+    log(f"bench: batched {ms_batched:.3f} ms/step, {value:.1f} Mpx/s")
+
+    # ---- per-view path ------------------------------------------------------
+    per_view = None
+    if not args.no_per_view:
+        views = []
+        pix_off = 0
+        for c in range(cams.n):
+            one = cams.subset([c])
+            r = Rasterizer(one, off, device=dev, capacity=1 << 24, **cfgkw)
+            r.forward(sp, check_capacity=True)
+            torch.cuda.synchronize()
+            r._alloc(int(r.n_isect() * 1.05) + 4096)
+            npx = int(cams.width[c]) * int(cams.height[c])
+            g_v = G_all[3 * pix_off: 3 * (pix_off + npx)]
+            pix_off += npx
+            views.append((r, g_v, {k: torch.empty_like(v) for k, v in sp.items()}))
+
+        def step_per_view():
+            for r, g_v, gr in views:
+                r.project(sp)
+                r.bin_sort()
+                if r.n_isect() > r.capacity:        # host read-back, as a per-view loop does
+                    raise RuntimeError("per-view capacity overflow")
+                r.rasterize_fwd()
+                r.rasterize_bwd(sp, g_v, gr)
+
+        for _ in range(args.warmup):
+            step_per_view()
+        torch.cuda.synchronize()
+        log(f"bench: timing {args.steps} per-view steps")
+        e0.record()
+        for _ in range(args.steps):
+            step_per_view()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_pv = e0.elapsed_time(e1) / args.steps
+        per_view = dict(value=round(P / (ms_pv * 1e-3) / 1e6, 3), ms_per_step=round(ms_pv, 3),
+                        batched_over_per_view=round(ms_pv / ms_batched, 3))
+        log(f"bench: per-view {ms_pv:.3f} ms/step, ratio {ms_pv / ms_batched:.3f}")
+        del views
+
+    # ---- roofline of the dominant kernel --------------------------------------
+    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, K=16, Q=Q)
+    kernels = []
+    for name, launches, total in ktimes:
+        kernels.append(dict(kernel=name, launches=launches, avg_ms=round(total / launches, 4),
+                            total_ms_per_step=round(total / args.steps, 4)))
+    roof = None
+    if kernels:
+        dom = kernels[0]
+        cost = kernel_cost(dom["kernel"], w)
+        if cost is not None:
+            bound, amount, unit = cost
+            launches_per_step = dom["launches"] / args.steps
+            per_launch = amount / launches_per_step if bound == "hbm" else amount
+            sec = dom["avg_ms"] * 1e-3
+            if bound == "hbm":
+                achieved = per_launch / sec / 1e9
+                peak, u = HBM_PEAK_GBS, "GB/s"
+            else:
+                achieved = per_launch / sec / 1e12
+                peak, u = FP64_VEC_PEAK_TFLOPS, "TFLOP/s"
+            roof = dict(kernel=dom["kernel"], bound=bound, achieved=round(achieved, 3), peak=peak,
+                        unit=u, frac=round(achieved / peak, 4),
+                        traffic=read_traffic(dom["kernel"]),
+                        algorithmic_per_launch=per_launch, avg_launch_ms=dom["avg_ms"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on a bounded sample (host CPU)")
+        cpu = cpu_baseline(scene, cams)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "3.2M splats SH3, log-scale N(-4,1), 8 views 1920x1080 on a "
+                               "radius-4 sphere, fwd+bwd, batched",
+                   "views": cams.n, "pixels_per_step": P, "n_isect": n_isect,
+                   "pairs_to_last": Q, "ags": bool(args.ags), "tile": "16x16",
+                   "parallelism": "single GPU"},
+        "per_view": per_view,
+        "roofline": roof,
+        "kernels": kernels[:12],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

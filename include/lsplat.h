@@ -244,6 +244,25 @@ ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* splats,
                            int64_t isect_capacity, const float* final_T, const int32_t* last,
                            const float* dL_dimage, const ls_grads* grads, void* stream);
 
+/*
+ * Kernel timing (tracing).  While enabled, every kernel the library enqueues
+ * is bracketed by a pair of HIP events recorded on the same stream.
+ * ls_profile_read waits for the recorded events, adds their elapsed times
+ * into per-kernel totals and writes up to `capacity` entries (kernel name,
+ * launches, total milliseconds) sorted by total time, longest first; *count
+ * receives the number of distinct kernels.  reset != 0 clears the totals.
+ * Not thread-safe; the library creates its events on first use and keeps them
+ * (a few hundred) until the process ends.
+ */
+typedef struct ls_kernel_time {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} ls_kernel_time;
+
+ls_status ls_profile_enable(int enable);
+ls_status ls_profile_read(ls_kernel_time* out, int capacity, int* count, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,10 @@ class Layout(C.Structure):
                 ("n_isect", C.c_size_t), ("grad2d", C.c_size_t), ("scratch", C.c_size_t)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -79,6 +83,8 @@ def _load() -> C.CDLL:
                               C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
         "ls_rasterize_bwd": ([P(Config), P(Splats), P(Cams), C.c_void_p, C.c_size_t, C.c_int64,
                               C.c_void_p, C.c_void_p, C.c_void_p, P(Grads), C.c_void_p], C.c_int),
+        "ls_profile_enable": ([C.c_int], C.c_int),
+        "ls_profile_read": ([P(KernelTime), C.c_int, P(C.c_int), C.c_int], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -89,7 +95,8 @@ def _load() -> C.CDLL:
 
 LIB = _load()
 EXPORTS = ("ls_version", "ls_last_error", "ls_workspace_size", "ls_workspace_layout",
-           "ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd")
+           "ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd",
+           "ls_profile_enable", "ls_profile_read")
 
 
 def _check(st: int):
@@ -178,3 +185,17 @@ def ls_rasterize_bwd(cfg, splats: Splats, cams: CamerasHost, ws, capacity, final
     _check(LIB.ls_rasterize_bwd(C.byref(cfg), C.byref(splats), C.byref(cams.c), _ptr(ws),
                                 ws.numel(), capacity, _ptr(final_T), _ptr(last),
                                 _ptr(dL_dimage), C.byref(grads), _stream(stream)))
+
+
+def ls_profile_enable(on: bool = True):
+    _check(LIB.ls_profile_enable(1 if on else 0))
+
+
+def ls_profile_read(reset: bool = True) -> list[tuple[str, int, float]]:
+    """[(kernel, launches, total_ms)] longest first; waits for the events."""
+    cap = 64
+    arr = (KernelTime * cap)()
+    n = C.c_int(0)
+    _check(LIB.ls_profile_read(arr, cap, C.byref(n), 1 if reset else 0))
+    return [(arr[i].name.decode(), int(arr[i].launches), float(arr[i].total_ms))
+            for i in range(min(n.value, cap))]

@@ -439,16 +439,28 @@ struct SortBufs {
 
 // One LSD pass; returns the launch error.
 template <bool kIdent, bool kWriteKeys>
-hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                      const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int G,
-                      uint32_t* hist, uint32_t* tot, hipStream_t s) {
-  hipLaunchKernelGGL(radix_upsweep, dim3(G), dim3(kSortThreads), 0, s, kin, n_dev, n_host, cap,
-                     shift, G, hist);
-  hipLaunchKernelGGL(radix_scan_rows, dim3(256), dim3(256), 0, s, hist, G, tot);
-  hipLaunchKernelGGL((radix_downsweep<kIdent, kWriteKeys>), dim3(G), dim3(kSortThreads), 0, s, kin,
-                     vin, kout, vout, n_dev, n_host, cap, shift, G, hist, tot);
+hipError_t radix_pass(const char* const names[3], const uint32_t* kin, const uint32_t* vin,
+                      uint32_t* kout, uint32_t* vout, const int64_t* n_dev, int64_t n_host,
+                      int64_t cap, int shift, int G, uint32_t* hist, uint32_t* tot, hipStream_t s) {
+  {
+    ProfScope ps(names[0], s);
+    hipLaunchKernelGGL(radix_upsweep, dim3(G), dim3(kSortThreads), 0, s, kin, n_dev, n_host, cap,
+                       shift, G, hist);
+  }
+  {
+    ProfScope ps(names[1], s);
+    hipLaunchKernelGGL(radix_scan_rows, dim3(256), dim3(256), 0, s, hist, G, tot);
+  }
+  {
+    ProfScope ps(names[2], s);
+    hipLaunchKernelGGL((radix_downsweep<kIdent, kWriteKeys>), dim3(G), dim3(kSortThreads), 0, s,
+                       kin, vin, kout, vout, n_dev, n_host, cap, shift, G, hist, tot);
+  }
   return hipGetLastError();
 }
+
+const char* const kPreNames[3] = {"presort_upsweep", "presort_scan", "presort_downsweep"};
+const char* const kTileNames[3] = {"tilesort_upsweep", "tilesort_scan", "tilesort_downsweep"};
 
 }  // namespace
 
@@ -471,16 +483,17 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
     uint32_t* kB = (uint32_t*)(ws + p.pre_keys_b);
     uint32_t* vB = (uint32_t*)(ws + p.pre_vals_b);
     const int G = p.pre_blocks;
-    if ((e = radix_pass<true, true>(dkey, nullptr, kB, vB, nullptr, M, M, 0, G, hist, tot, s))) return e;
-    if ((e = radix_pass<false, true>(kB, vB, kA, vA, nullptr, M, M, 8, G, hist, tot, s))) return e;
-    if ((e = radix_pass<false, true>(kA, vA, kB, vB, nullptr, M, M, 16, G, hist, tot, s))) return e;
-    if ((e = radix_pass<false, false>(kB, vB, nullptr, order, nullptr, M, M, 24, G, hist, tot, s)))
+    if ((e = radix_pass<true, true>(kPreNames, dkey, nullptr, kB, vB, nullptr, M, M, 0, G, hist, tot, s))) return e;
+    if ((e = radix_pass<false, true>(kPreNames, kB, vB, kA, vA, nullptr, M, M, 8, G, hist, tot, s))) return e;
+    if ((e = radix_pass<false, true>(kPreNames, kA, vA, kB, vB, nullptr, M, M, 16, G, hist, tot, s))) return e;
+    if ((e = radix_pass<false, false>(kPreNames, kB, vB, nullptr, order, nullptr, M, M, 24, G, hist, tot, s)))
       return e;
   }
   // 2. scan of tile counts in depth order
   {
     int64_t* part = (int64_t*)(ws + p.scan_part);
     const int B = p.scan_blocks;
+    ProfScope ps("scan", s);
     if (M > 0) {
       hipLaunchKernelGGL(scan_reduce, dim3(B), dim3(kScanThreads), 0, s, order, ntiles, M, B, part);
     }
@@ -504,15 +517,18 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
     uint32_t* v0 = (passes % 2 == 0) ? vA : vB;
     int64_t spans = (p.cap + kKeygenSpan - 1) / kKeygenSpan;
     int blocks = (int)std::min<int64_t>(spans, kKeygenBlocks);
-    hipLaunchKernelGGL(keygen_kernel, dim3(blocks), dim3(kKeygenThreads), 0, s, order, isect_off,
-                       (const ushort4*)(ws + p.lay.rect), cams, p.C, M, n_isect, p.cap, k0, v0);
+    {
+      ProfScope ps("keygen", s);
+      hipLaunchKernelGGL(keygen_kernel, dim3(blocks), dim3(kKeygenThreads), 0, s, order, isect_off,
+                         (const ushort4*)(ws + p.lay.rect), cams, p.C, M, n_isect, p.cap, k0, v0);
+    }
     if ((e = hipGetLastError())) return e;
     const int G = p.sort_blocks;
     uint32_t *kin = k0, *vin = v0;
     for (int pass = 0; pass < passes; ++pass) {
       uint32_t* kout = (kin == kA) ? kB : kA;
       uint32_t* vout = (vin == vA) ? vB : vA;
-      if ((e = radix_pass<false, true>(kin, vin, kout, vout, n_isect, 0, p.cap, 8 * pass, G, hist,
+      if ((e = radix_pass<false, true>(kTileNames, kin, vin, kout, vout, n_isect, 0, p.cap, 8 * pass, G, hist,
                                        tot, s)))
         return e;
       kin = kout;
@@ -522,6 +538,7 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
   // 5. ranges
   {
     int64_t blocks = std::min<int64_t>((p.T + 1 + kRangeThreads - 1) / kRangeThreads, 4096);
+    ProfScope ps("ranges", s);
     hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(kRangeThreads), 0, s, kA, n_isect,
                        p.cap, p.T, (int64_t*)(ws + p.lay.ranges));
     if ((e = hipGetLastError())) return e;

@@ -94,6 +94,16 @@ __device__ __forceinline__ float wave_sum_to_lane63(float x) {
   return x;
 }
 
+// Kernel timing: while profiling is enabled, a ProfScope brackets the launches
+// made during its lifetime with two events on the launch stream.
+struct ProfScope {
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  const char* name_;
+  hipStream_t s_;
+  int slot_;
+};
+
 // host launchers (each returns hipSuccess or the launch error)
 hipError_t launch_cam_setup(const Plan& p, const ls_cameras* cams, char* ws, hipStream_t s);
 hipError_t launch_project(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,

@@ -509,8 +509,11 @@ hipError_t launch_cam_setup(const Plan& p, const ls_cameras* cams, char* ws, hip
       a.pair_off[i] = p.pair_off[c]; a.tile_off[i] = p.tile_off[c]; a.pix_off[i] = p.pix_off[c];
       a.lo[i] = p.splat_lo[c]; a.hi[i] = p.splat_hi[c];
     }
-    hipLaunchKernelGGL(cam_setup_kernel, dim3(1), dim3(kCamsPerSetup), 0, s, a, cams->viewmat,
-                       cams->intrin, out);
+    {
+      ProfScope ps("cam_setup", s);
+      hipLaunchKernelGGL(cam_setup_kernel, dim3(1), dim3(kCamsPerSetup), 0, s, a, cams->viewmat,
+                         cams->intrin, out);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -528,6 +531,7 @@ hipError_t launch_project(const Plan& p, const ls_config* cfg, const ls_splats* 
                      cfg->clip, cfg->near_z, cfg->far_z, cfg->tile_w, cfg->tile_h,              \
                      (ProjRec*)(ws + p.lay.proj), (ushort4*)(ws + p.lay.rect),                  \
                      (uint32_t*)(ws + p.lay.ntiles), (uint32_t*)(ws + p.lay.depth_key))
+  ProfScope ps("project", s);
   switch (cfg->sh_degree) {
     case 0: LS_PROJ(0); break;
     case 1: LS_PROJ(1); break;
@@ -548,6 +552,7 @@ hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_spla
                      sp->means, sp->scales, sp->quats, sp->sh, cfg->eps2d, cfg->clip,             \
                      (const float*)(ws + p.lay.grad2d), p.M, gr->means, gr->scales, gr->quats,    \
                      gr->opacity, gr->sh)
+  ProfScope ps("project_bwd", s);
   switch (cfg->sh_degree) {
     case 0: LS_PBWD(0); break;
     case 1: LS_PBWD(1); break;

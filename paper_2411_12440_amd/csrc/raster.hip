@@ -350,6 +350,7 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
   const int npix = cfg->tile_w * cfg->tile_h;
   const int batch = cfg->batch ? cfg->batch : npix;
   dim3 grid((unsigned)p.T);
+  ProfScope ps("raster_fwd", s);
 #define LS_FWD(TW_, TH_)                                                                        \
   hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
                      vals, proj, p.M, batch, rp, image, final_T, last)
@@ -368,6 +369,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
   const int64_t ng = (int64_t)kGrad2d * p.M;
   if (ng > 0) {
     int64_t blocks = std::min<int64_t>((ng + 255) / 256, 8192);
+    ProfScope ps("zero_grad2d", s);
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, grad2d, ng);
   }
   if (p.T > 0) {
@@ -379,6 +381,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     const int npix = cfg->tile_w * cfg->tile_h;
     const int batch = cfg->batch ? cfg->batch : npix;
     dim3 grid((unsigned)p.T);
+    ProfScope ps("raster_bwd", s);
 #define LS_BWD(TW_, TH_)                                                                         \
   hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
                      vals, proj, p.M, batch, rp, final_T, last, dL_dimage, grad2d)
