@@ -141,6 +141,8 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   int64_t sb = (p->M + 1 + kScanThreads * 16 - 1) / (kScanThreads * 16);
   p->scan_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(sb, kMaxScanBlocks));
   p->scan_part = take(8 * (size_t)(p->scan_blocks + 1));
+  p->n_spans = (cap + kKeygenSpan - 1) / kKeygenSpan + 1;
+  p->span_owner = take(4 * (size_t)p->n_spans);
   L.total_bytes = off;
   return LS_OK;
 }

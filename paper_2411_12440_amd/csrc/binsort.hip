@@ -31,7 +31,6 @@ namespace lsplat {
 
 namespace {
 
-constexpr int kKeygenSpan = 2048;   // output entries per keygen block iteration
 constexpr int kKeygenThreads = 256;
 constexpr int kKeygenBlocks = 4096;
 constexpr int kRangeThreads = 256;
@@ -263,11 +262,18 @@ __global__ void scan_parts(int64_t* __restrict__ part, int B, int64_t M,
   *n_isect = run;
 }
 
+// Also records, for every key-generation span of kKeygenSpan output entries,
+// the pair that owns the span's first entry (span_owner[s]); the entry past
+// the last span names the last pair with entries.
 __global__ __launch_bounds__(kScanThreads) void scan_down(const uint32_t* __restrict__ order,
                                                           const uint32_t* __restrict__ ntiles,
                                                           int64_t M, int B,
                                                           const int64_t* __restrict__ part,
-                                                          int64_t* __restrict__ isect_off) {
+                                                          int64_t* __restrict__ isect_off,
+                                                          const int64_t* __restrict__ n_isect,
+                                                          uint32_t* __restrict__ span_owner,
+                                                          int64_t n_spans) {
+  const int64_t n_total = *n_isect;
   __shared__ int64_t s_w[kScanThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t beg, end;
@@ -302,7 +308,18 @@ __global__ __launch_bounds__(kScanThreads) void scan_down(const uint32_t* __rest
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       int64_t p = tb + (int64_t)tid * kPer + k;
-      if (p < end) isect_off[p] = base;
+      if (p < end) {
+        isect_off[p] = base;
+        if (v[k] > 0) {
+          for (int64_t sp = (base + kKeygenSpan - 1) / kKeygenSpan;
+               sp * kKeygenSpan < base + v[k] && sp < n_spans; ++sp)
+            span_owner[sp] = (uint32_t)p;
+          if (base + v[k] == n_total) {
+            const int64_t term = (n_total + kKeygenSpan - 1) / kKeygenSpan;
+            if (term < n_spans) span_owner[term] = (uint32_t)p;
+          }
+        }
+      }
       base += v[k];
     }
     run += tot;
@@ -335,8 +352,8 @@ __device__ __forceinline__ int cam_of_pair(const CamInfo* cams, int C, int64_t m
 __global__ __launch_bounds__(kKeygenThreads) void keygen_kernel(
     const uint32_t* __restrict__ order, const int64_t* __restrict__ isect_off,
     const ushort4* __restrict__ rect, const CamInfo* __restrict__ cams, int C, int64_t M,
-    const int64_t* __restrict__ n_isect, int64_t cap, uint32_t* __restrict__ keys,
-    uint32_t* __restrict__ vals) {
+    const int64_t* __restrict__ n_isect, int64_t cap, const uint32_t* __restrict__ span_owner,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ int32_t s_owner[kKeygenSpan];
   __shared__ int64_t s_off[kKeygenSpan];
   __shared__ uint32_t s_m[kKeygenSpan];
@@ -350,8 +367,15 @@ __global__ __launch_bounds__(kKeygenThreads) void keygen_kernel(
   if (n > cap) return;
   for (int64_t k0 = (int64_t)blockIdx.x * kKeygenSpan; k0 < n; k0 += (int64_t)gridDim.x * kKeygenSpan) {
     const int64_t k1 = (k0 + kKeygenSpan < n) ? k0 + kKeygenSpan : n;
-    if (tid == 0) s_plo = upper_bound_i64(isect_off, M + 1, k0) - 1;
-    if (tid == 1) s_phi = upper_bound_i64(isect_off, M + 1, k1 - 1) - 1;
+    if (tid == 0) {
+      const int64_t sp = k0 / kKeygenSpan;
+      int64_t lo = span_owner[sp], hi = span_owner[sp + 1];
+      if (lo > M - 1) lo = M - 1;
+      if (hi > M - 1) hi = M - 1;
+      if (hi < lo) hi = lo;
+      s_plo = lo;
+      s_phi = hi;
+    }
     for (int i = tid; i < kKeygenSpan; i += kKeygenThreads) s_owner[i] = 0;
     __syncthreads();
     const int64_t plo = s_plo, phi = s_phi;
@@ -501,7 +525,7 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
                        n_isect);
     if (M > 0) {
       hipLaunchKernelGGL(scan_down, dim3(B), dim3(kScanThreads), 0, s, order, ntiles, M, B, part,
-                         isect_off);
+                         isect_off, n_isect, (uint32_t*)(ws + p.span_owner), p.n_spans);
     }
     if ((e = hipGetLastError())) return e;
   }
@@ -520,7 +544,8 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
     {
       ProfScope ps("keygen", s);
       hipLaunchKernelGGL(keygen_kernel, dim3(blocks), dim3(kKeygenThreads), 0, s, order, isect_off,
-                         (const ushort4*)(ws + p.lay.rect), cams, p.C, M, n_isect, p.cap, k0, v0);
+                         (const ushort4*)(ws + p.lay.rect), cams, p.C, M, n_isect, p.cap,
+                         (const uint32_t*)(ws + p.span_owner), k0, v0);
     }
     if ((e = hipGetLastError())) return e;
     const int G = p.sort_blocks;

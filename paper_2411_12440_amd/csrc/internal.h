@@ -60,7 +60,8 @@ struct Plan {
   ls_layout lay{};
   // scratch sub-allocations (byte offsets from the workspace base)
   size_t sort_keys_b = 0, sort_vals_b = 0, pre_keys_a = 0, pre_keys_b = 0, pre_vals_a = 0, pre_vals_b = 0,
-         hist = 0, digit_tot = 0, scan_part = 0, flags = 0;
+         hist = 0, digit_tot = 0, scan_part = 0, flags = 0, span_owner = 0;
+  int64_t n_spans = 0;        // entries of span_owner: ceil(cap / kKeygenSpan) + 1
   int32_t sort_blocks = 0;    // radix sort grid for the intersection sort
   int32_t pre_blocks = 0;     // radix sort grid for the depth presort
   int32_t scan_blocks = 0;
@@ -72,6 +73,7 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxSortBlocks = 1024;
 constexpr int kScanThreads = 256;
+constexpr int kKeygenSpan = 2048;   // output entries per key-generation block iteration
 constexpr int kMaxScanBlocks = 1024;
 
 // ---------------------------------------------------------------------------

@@ -46,10 +46,6 @@ struct PairEval {
   bool clamped;
 };
 
-__device__ __forceinline__ double quad_form(double dx, double dy, double A, double B2, double C) {
-  return fma(dx, fma(A, dx, B2 * dy), (C * dy) * dy);
-}
-
 __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterParams& rp) {
 #pragma clang fp contract(off)
   PairEval e;
@@ -81,25 +77,106 @@ __device__ __forceinline__ int cam_of_tile(const CamInfo* cams, int C, int64_t t
   return lo;
 }
 
+// LDS staging of one batch of a tile's list.  Each entry becomes the
+// coefficients of its quadratic form in the tile's local pixel coordinates
+// (lx, ly) = (0..TW-1, 0..TH-1):
+//   D'^2 = qa lx^2 + qb lx ly + qc ly^2 + qd lx + qe ly + qf,
+// five FP64 FMAs per pixel.  Entries whose support ellipse misses the tile's
+// pixel-centre rectangle are dropped and the survivors compacted in list
+// order, so the per-pixel loop only sees splats that can touch the tile.
 template <int NT>
 struct Stage {
+  double qa[NT], qb[NT], qc[NT], qd[NT], qe[NT], qf[NT];
   double ox[NT], oy[NT];     // centre relative to the tile's first pixel centre
-  double A[NT], B2[NT], C[NT];
   float r[NT], g[NT], b[NT], o[NT];
+  int32_t pos[NT];           // position in the tile list
+  uint32_t m[NT];            // pair id
+  int32_t wcount[NT / 64];
 };
 
-template <int NT>
-__device__ __forceinline__ void stage_one(Stage<NT>& st, int i, const ProjRec& rec, double x0c,
-                                          double y0c) {
-  st.ox[i] = rec.mx - x0c;
-  st.oy[i] = rec.my - y0c;
-  st.A[i] = rec.A;
-  st.B2[i] = 2.0 * rec.B;
-  st.C[i] = rec.C;
-  st.r[i] = rec.r;
-  st.g[i] = rec.g;
-  st.b[i] = rec.b;
-  st.o[i] = rec.o;
+__device__ __forceinline__ double quad_local(double qa, double qb, double qc, double qd, double qe,
+                                             double qf, double lx, double ly, double lx2,
+                                             double lxy, double ly2) {
+  return fma(qa, lx2, fma(qb, lxy, fma(qc, ly2, fma(qd, lx, fma(qe, ly, qf)))));
+}
+
+// true if min over [0, w] x [0, h] of A dx^2 + 2B dx dy + C dy^2 (dx = x - ox,
+// dy = y - oy) may be below lam2; a relative margin keeps every splat that the
+// per-pixel evaluation could still find inside its support.
+__device__ __forceinline__ bool ellipse_hits_rect(double ox, double oy, double A, double B,
+                                                  double C, double lam2, double w, double h) {
+  if (ox >= 0.0 && ox <= w && oy >= 0.0 && oy <= h) return true;
+  double best = 1e300;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double dx = (e ? w : 0.0) - ox;
+    const double y = fmin(h, fmax(0.0, oy - B * dx / C));
+    const double dy = y - oy;
+    best = fmin(best, A * dx * dx + 2.0 * B * dx * dy + C * dy * dy);
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double dy = (e ? h : 0.0) - oy;
+    const double x = fmin(w, fmax(0.0, ox - B * dy / A));
+    const double dx = x - ox;
+    best = fmin(best, A * dx * dx + 2.0 * B * dx * dy + C * dy * dy);
+  }
+  return best < lam2 * (1.0 + 1e-6);
+}
+
+// Stage list positions [p0, p0 + nb) of a tile whose list starts at `start`;
+// returns the number of surviving entries (block-uniform).
+template <int TW, int TH>
+__device__ __forceinline__ int stage_batch(Stage<TW * TH>& st, const uint32_t* __restrict__ vals,
+                                           const ProjRec* __restrict__ proj, int64_t M,
+                                           int64_t start, int32_t p0, int nb, double x0c,
+                                           double y0c, double lam2) {
+  constexpr int NT = TW * TH;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  bool keep = false;
+  uint32_t m = 0;
+  ProjRec rec;
+  double ox = 0.0, oy = 0.0;
+  if (tid < nb) {
+    m = vals[start + p0 + tid];
+    if (m >= (uint64_t)M) m = 0;   // unreachable for a valid list
+    rec = proj[m];
+    ox = rec.mx - x0c;
+    oy = rec.my - y0c;
+    keep = ellipse_hits_rect(ox, oy, rec.A, rec.B, rec.C, lam2, (double)(TW - 1), (double)(TH - 1));
+  }
+  const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
+  if (lane == 0) st.wcount[wave] = (int32_t)__popcll(bal);
+  __syncthreads();
+  int base = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const int c = st.wcount[w];
+    base += (w < wave) ? c : 0;
+    total += c;
+  }
+  if (keep) {
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int k = base + (int)__popcll(bal & lt);
+    const double A = rec.A, B = rec.B, C = rec.C;
+    const double u = A * ox + B * oy, v = B * ox + C * oy;
+    st.qa[k] = A;
+    st.qb[k] = 2.0 * B;
+    st.qc[k] = C;
+    st.qd[k] = -2.0 * u;
+    st.qe[k] = -2.0 * v;
+    st.qf[k] = ox * u + oy * v;
+    st.ox[k] = ox;
+    st.oy[k] = oy;
+    st.r[k] = rec.r;
+    st.g[k] = rec.g;
+    st.b[k] = rec.b;
+    st.o[k] = rec.o;
+    st.pos[k] = p0 + tid;
+    st.m[k] = m;
+  }
+  __syncthreads();
+  return total;
 }
 
 template <int TW, int TH>
@@ -116,31 +193,28 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   const CamInfo& ci = cams[c];
   const int64_t local = tile - ci.tile_off;
   const int ty = (int)(local / ci.GX), tx = (int)(local % ci.GX);
-  const int lx = tid % TW, ly = tid / TW;
-  const int px = tx * TW + lx, py = ty * TH + ly;
+  const int lxi = tid % TW, lyi = tid / TW;
+  const int px = tx * TW + lxi, py = ty * TH + lyi;
   const bool inside = (px < ci.W) && (py < ci.H);
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
-  const double lxd = (double)lx, lyd = (double)ly;
-  const int64_t start = ranges[tile], end = ranges[tile + 1];
+  const double lx = (double)lxi, ly = (double)lyi;
+  const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
+  const int64_t start = ranges[tile];
+  const int32_t len = (int32_t)(ranges[tile + 1] - start);
 
   double T = 1.0, cr = 0.0, cg = 0.0, cb = 0.0;
   int32_t lastc = 0;
   bool done = !inside;
-  for (int64_t b0 = start; b0 < end; b0 += batch) {
+  for (int32_t p0 = 0; p0 < len; p0 += batch) {
     if (__syncthreads_count(!done) == 0) break;
-    const int nb = (int)((end - b0) < batch ? (end - b0) : batch);
-    if (tid < nb) {
-      const uint32_t m = vals[b0 + tid];
-      stage_one(st, tid, proj[m < (uint64_t)M ? m : 0], x0c, y0c);
-    }
-    __syncthreads();
+    const int nb = (len - p0) < batch ? (len - p0) : batch;
+    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, start, p0, nb, x0c, y0c, rp.lam2);
     if (!done) {
-      for (int j = 0; j < nb; ++j) {
-        const double dx = lxd - st.ox[j];
-        const double dy = lyd - st.oy[j];
-        const double q = quad_form(dx, dy, st.A[j], st.B2[j], st.C[j]);
+      for (int k = 0; k < cnt; ++k) {
+        const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
+                                    lx, ly, lx2, lxy, ly2);
         if (!(q < rp.lam2)) continue;
-        const PairEval e = pair_eval(q, (double)st.o[j], rp);
+        const PairEval e = pair_eval(q, (double)st.o[k], rp);
         if (!(e.alpha > 0.0) || e.alpha < rp.amin) continue;
         const double Tn = T * e.oma;
         if (Tn < rp.tmin) {
@@ -148,11 +222,11 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
           break;
         }
         const double w = e.alpha * T;
-        cr = fma((double)st.r[j], w, cr);
-        cg = fma((double)st.g[j], w, cg);
-        cb = fma((double)st.b[j], w, cb);
+        cr = fma((double)st.r[k], w, cr);
+        cg = fma((double)st.g[k], w, cg);
+        cb = fma((double)st.b[k], w, cb);
         T = Tn;
-        lastc = (int32_t)(b0 - start) + j + 1;
+        lastc = st.pos[k] + 1;
       }
     }
   }
@@ -177,7 +251,6 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
   __shared__ Stage<NT> st;
-  __shared__ uint32_t s_m[NT];
   __shared__ float s_acc[kGrad2d][NT];
   __shared__ int32_t s_max[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -186,11 +259,12 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   const CamInfo& ci = cams[c];
   const int64_t local = tile - ci.tile_off;
   const int ty = (int)(local / ci.GX), tx = (int)(local % ci.GX);
-  const int lx = tid % TW, ly = tid / TW;
-  const int px = tx * TW + lx, py = ty * TH + ly;
+  const int lxi = tid % TW, lyi = tid / TW;
+  const int px = tx * TW + lxi, py = ty * TH + lyi;
   const bool inside = (px < ci.W) && (py < ci.H);
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
-  const double lxd = (double)lx, lyd = (double)ly;
+  const double lx = (double)lxi, ly = (double)lyi;
+  const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
   const int64_t start = ranges[tile];
   const int64_t len = ranges[tile + 1] - start;
 
@@ -223,36 +297,27 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
 
   for (int32_t hi = maxlast; hi > 0; hi -= batch) {
     const int32_t lo = hi - batch > 0 ? hi - batch : 0;
-    const int nb = hi - lo;
     __syncthreads();
-    if (tid < nb) {
-      uint32_t m = vals[start + lo + tid];
-      if (m >= (uint64_t)M) m = 0;   // unreachable for a valid list
-      s_m[tid] = m;
-      stage_one(st, tid, proj[m], x0c, y0c);
-    }
+    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, start, lo, hi - lo, x0c, y0c, rp.lam2);
     for (int i = tid; i < kGrad2d * NT; i += NT) (&s_acc[0][0])[i] = 0.f;
     __syncthreads();
-    for (int jj = nb - 1; jj >= 0; --jj) {
-      const int32_t j = lo + jj;
+    for (int k = cnt - 1; k >= 0; --k) {
       float gv[kGrad2d];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.f;
       bool contrib = false;
-      if (j < mylast) {
-        const double dx = lxd - st.ox[jj];
-        const double dy = lyd - st.oy[jj];
-        const double A = st.A[jj], B2 = st.B2[jj], Cc = st.C[jj];
-        const double q = quad_form(dx, dy, A, B2, Cc);
+      if (st.pos[k] < mylast) {
+        const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
+                                    lx, ly, lx2, lxy, ly2);
         if (q < rp.lam2) {
-          const double o = (double)st.o[jj];
+          const double o = (double)st.o[k];
           const PairEval e = pair_eval(q, o, rp);
           if (e.alpha > 0.0 && e.alpha >= rp.amin) {
             contrib = true;
             const double inv = 1.0 / e.oma;
             const double Ti = T * inv;
             const double w = e.alpha * Ti;
-            const double cr = st.r[jj], cg = st.g[jj], cb = st.b[jj];
+            const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
             double g_r = w * G0, g_g = w * G1, g_b = w * G2;
             const double GdC = G0 * cr + G1 * cg + G2 * cb;
             const double GdS = G0 * S0 + G1 * S1 + G2 * S2;
@@ -273,8 +338,10 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
               const double dLdD = -(o * dLda) * rp.inv_lam * om;
               if (e.D > 0.0) {
                 const double gq = 0.5 * dLdD / e.D;
-                gv[0] = (float)(-2.0 * gq * (A * dx + 0.5 * B2 * dy));
-                gv[1] = (float)(-2.0 * gq * (0.5 * B2 * dx + Cc * dy));
+                const double dx = lx - st.ox[k], dy = ly - st.oy[k];
+                const double A = st.qa[k], B = 0.5 * st.qb[k], Cc = st.qc[k];
+                gv[0] = (float)(-2.0 * gq * (A * dx + B * dy));
+                gv[1] = (float)(-2.0 * gq * (B * dx + Cc * dy));
                 gv[2] = (float)(gq * dx * dx);
                 gv[3] = (float)(2.0 * gq * dx * dy);
                 gv[4] = (float)(gq * dy * dy);
@@ -297,14 +364,14 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
       if (__builtin_amdgcn_ballot_w64(contrib) != 0ull) {
 #pragma unroll
         for (int f = 0; f < kGrad2d; ++f) {
-          const float s = wave_sum_to_lane63(gv[f]);
-          if (lane == 63 && s != 0.f) atomicAdd(&s_acc[f][jj], s);
+          const float sum = wave_sum_to_lane63(gv[f]);
+          if (lane == 63 && sum != 0.f) atomicAdd(&s_acc[f][k], sum);
         }
       }
     }
     __syncthreads();
-    if (tid < nb) {
-      const int64_t m = (int64_t)s_m[tid];
+    if (tid < cnt) {
+      const int64_t m = (int64_t)st.m[tid];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) {
         const float v = s_acc[f][tid];
