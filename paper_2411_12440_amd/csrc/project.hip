@@ -214,6 +214,34 @@ __device__ __forceinline__ void sh_grad_dot(int deg, double x, double y, double 
   g[0] = gx; g[1] = gy; g[2] = gz;
 }
 
+// raw colour 0.5 + sum_k Y_k(d) sh_k (before the clamp); shc holds the
+// splat's coefficients as [k][channel].
+template <int DEG>
+__device__ __forceinline__ void sh_raw(double x, double y, double z, const float* shc,
+                                       double raw[3]) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  double Y[16];
+  sh_eval(DEG, x, y, z, Y);
+  raw[0] = raw[1] = raw[2] = 0.5;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[k] * (double)shc[3 * k + ch];
+}
+
+// gd = sum_k (sum_c graw_c sh_kc) dY_k/dd
+template <int DEG>
+__device__ __forceinline__ void sh_dir_grad(double x, double y, double z, const float* shc,
+                                            const double graw[3], double gd[3]) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  double wk[16];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    wk[k] = graw[0] * (double)shc[3 * k] + graw[1] * (double)shc[3 * k + 1] +
+            graw[2] * (double)shc[3 * k + 2];
+  sh_grad_dot(DEG, x, y, z, wk, gd);
+}
+
 // FP64 geometry of one (camera, splat) pair, shared by forward and backward.
 struct Geo {
   double q[4], qn;         // normalised quaternion and the input norm
@@ -344,8 +372,7 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
     const float* __restrict__ scales, const float* __restrict__ quats,
     const float* __restrict__ sh, float eps, float clip, const float* __restrict__ grad2d,
     int64_t M, float* __restrict__ g_means, float* __restrict__ g_scales,
-    float* __restrict__ g_quats, float* __restrict__ g_opac, float* __restrict__ g_sh) {
-  constexpr int K = (DEG + 1) * (DEG + 1);
+    float* __restrict__ g_quats, float* __restrict__ g_opac) {
   int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
   if (i >= N) return;
   double mu[3], s[3], q[4];
@@ -355,9 +382,6 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
   }
   for (int k = 0; k < 4; ++k) q[k] = quats[k * N + i];
   double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0;
-  float gsh[K * 3];
-#pragma unroll
-  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
 
   for (int c = 0; c < C; ++c) {
     const CamInfo& ci = cams[c];
@@ -455,34 +479,6 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
                     y * gR[5] + x * gR[6] + y * gR[7]);
     double dq = w * gqh[0] + x * gqh[1] + y * gqh[2] + z * gqh[3];
     for (int k = 0; k < 4; ++k) gq[k] += (gqh[k] - g.q[k] * dq) / g.qn;
-    // colour
-    double vx = mu[0] - ci.campos[0], vy = mu[1] - ci.campos[1], vz = mu[2] - ci.campos[2];
-    double dist = sqrt(vx * vx + vy * vy + vz * vz);
-    double dx = vx / dist, dy = vy / dist, dz = vz / dist;
-    double Y[16];
-    sh_eval(DEG, dx, dy, dz, Y);
-    double raw[3] = {0.5, 0.5, 0.5};
-    for (int k = 0; k < K; ++k)
-      for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[k] * (double)sh[(int64_t)(3 * k + ch) * N + i];
-    double graw[3];
-    for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] > 0.0 ? (double)g2[6 + ch] : 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) gsh[3 * k + ch] += (float)(Y[k] * graw[ch]);
-    if (DEG > 0) {
-      double wk[16];
-      for (int k = 0; k < K; ++k) {
-        wk[k] = 0.0;
-        for (int ch = 0; ch < 3; ++ch) wk[k] += graw[ch] * (double)sh[(int64_t)(3 * k + ch) * N + i];
-      }
-      double gd[3];
-      sh_grad_dot(DEG, dx, dy, dz, wk, gd);
-      double dd = dx * gd[0] + dy * gd[1] + dz * gd[2];
-      gmu[0] += (gd[0] - dx * dd) / dist;
-      gmu[1] += (gd[1] - dy * dd) / dist;
-      gmu[2] += (gd[2] - dz * dd) / dist;
-    }
   }
   for (int k = 0; k < 3; ++k) {
     g_means[k * N + i] = (float)gmu[k];
@@ -490,8 +486,61 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
   }
   for (int k = 0; k < 4; ++k) g_quats[k * N + i] = (float)gq[k];
   g_opac[i] = (float)go;
+}
+
+// SH coefficient gradients: dL/dsh_kc = sum over cameras of Y_k(d) dL/drgb_c
+// where the colour clamp is inactive.  Kept apart from the geometry chain so
+// that neither kernel holds both working sets in registers.
+template <int DEG>
+__global__ __launch_bounds__(kProjThreads) void project_bwd_sh_kernel(
+    const CamInfo* __restrict__ cams, int C, int64_t N, const float* __restrict__ means,
+    const float* __restrict__ sh, const float* __restrict__ grad2d, int64_t M,
+    float* __restrict__ g_sh, float* __restrict__ g_means) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+  if (i >= N) return;
+  const double mu0 = means[i], mu1 = means[N + i], mu2 = means[2 * N + i];
+  float gsh[K * 3], shc[K * 3];
+  double gmv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) {
+    gsh[k] = 0.f;
+    shc[k] = sh[(int64_t)k * N + i];
+  }
+  for (int c = 0; c < C; ++c) {
+    const CamInfo& ci = cams[c];
+    if (i < ci.splat_lo || i >= ci.splat_hi) continue;
+    const int64_t m = ci.pair_off + (i - ci.splat_lo);
+    const float gr = grad2d[6 * M + m], gg = grad2d[7 * M + m], gb = grad2d[8 * M + m];
+    if (gr == 0.f && gg == 0.f && gb == 0.f) continue;
+    double vx = mu0 - ci.campos[0], vy = mu1 - ci.campos[1], vz = mu2 - ci.campos[2];
+    double inv = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
+    double dx = vx * inv, dy = vy * inv, dz = vz * inv;
+    double raw[3];
+    sh_raw<DEG>(dx, dy, dz, shc, raw);
+    const double graw[3] = {raw[0] > 0.0 ? (double)gr : 0.0, raw[1] > 0.0 ? (double)gg : 0.0,
+                            raw[2] > 0.0 ? (double)gb : 0.0};
+    double Y[16];
+    sh_eval(DEG, dx, dy, dz, Y);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gsh[3 * k + ch] += (float)(Y[k] * graw[ch]);
+    if (DEG > 0) {
+      // the view direction moves with the centre: d = v/|v|, v = mu - campos
+      double gd[3];
+      sh_dir_grad<DEG>(dx, dy, dz, shc, graw, gd);
+      const double dd = dx * gd[0] + dy * gd[1] + dz * gd[2];
+      gmv[0] += (gd[0] - dx * dd) * inv;
+      gmv[1] += (gd[1] - dy * dd) * inv;
+      gmv[2] += (gd[2] - dz * dd) * inv;
+    }
+  }
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) g_sh[(int64_t)k * N + i] = gsh[k];
+  if (DEG > 0) {
+    for (int k = 0; k < 3; ++k) g_means[k * N + i] = (float)((double)g_means[k * N + i] + gmv[k]);
+  }
 }
 
 }  // namespace
@@ -548,11 +597,21 @@ hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_spla
   const CamInfo* cams = (const CamInfo*)(ws + p.lay.cams);
   dim3 grid((unsigned)((p.N + kProjThreads - 1) / kProjThreads));
 #define LS_PBWD(D)                                                                                 \
-  hipLaunchKernelGGL(project_bwd_kernel<D>, grid, dim3(kProjThreads), 0, s, cams, p.C, p.N,       \
-                     sp->means, sp->scales, sp->quats, sp->sh, cfg->eps2d, cfg->clip,             \
-                     (const float*)(ws + p.lay.grad2d), p.M, gr->means, gr->scales, gr->quats,    \
-                     gr->opacity, gr->sh)
-  ProfScope ps("project_bwd", s);
+  do {                                                                                             \
+    {                                                                                              \
+      ProfScope ps("project_bwd", s);                                                              \
+      hipLaunchKernelGGL(project_bwd_kernel<D>, grid, dim3(kProjThreads), 0, s, cams, p.C, p.N,   \
+                         sp->means, sp->scales, sp->quats, sp->sh, cfg->eps2d, cfg->clip,         \
+                         (const float*)(ws + p.lay.grad2d), p.M, gr->means, gr->scales,           \
+                         gr->quats, gr->opacity);                                                 \
+    }                                                                                              \
+    {                                                                                              \
+      ProfScope ps("project_bwd_sh", s);                                                           \
+      hipLaunchKernelGGL(project_bwd_sh_kernel<D>, grid, dim3(kProjThreads), 0, s, cams, p.C, p.N, \
+                         sp->means, sp->sh, (const float*)(ws + p.lay.grad2d), p.M, gr->sh,       \
+                         gr->means);                                                              \
+    }                                                                                              \
+  } while (0)
   switch (cfg->sh_degree) {
     case 0: LS_PBWD(0); break;
     case 1: LS_PBWD(1); break;
