@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 100
+#define LSPLAT_VERSION 110
 
 typedef enum {
   LS_OK = 0,
@@ -78,6 +78,16 @@ typedef enum {
  * batch      Splats staged in LDS per batch in the raster kernels: 0 (= the
  *            tile's pixel count), 64, 128 or 256; must not exceed the tile's
  *            pixel count.
+ * depth_chunks  0 or 1: ls_bin_sort builds every tile's complete list.
+ *            K in 2..12: ls_bin_sort only orders the pairs by depth and scans
+ *            their tile counts; ls_rasterize_fwd then builds the lists in K
+ *            chunks of that order (the first M/2^(K-1) pairs, the next
+ *            M/2^(K-1), then M/2^(K-2), ..., the last M/2) and composites each
+ *            chunk before building the next.  A chunk skips every tile whose
+ *            pixels have all stopped (T would fall below t_min), so each
+ *            tile's list is the prefix of its complete list that the
+ *            composite can reach.  Images and gradients are identical to the
+ *            complete-list mode.
  */
 typedef struct ls_config {
   float lambda;
@@ -89,6 +99,7 @@ typedef struct ls_config {
   int32_t sh_degree;
   int32_t tile_w, tile_h;
   int32_t batch;
+  int32_t depth_chunks;
 } ls_config;
 
 /*
@@ -156,18 +167,27 @@ typedef struct ls_cameras {
  *              culled).
  *   order      [M] uint32: pair ids sorted by (depth_key, pair id).
  *   isect_off  [M+1] int64: exclusive scan of ntiles in `order`.
- *   keys       [cap] uint32: sorted global tile ids.
- *   vals       [cap] uint32: pair ids in (tile, depth, pair id) order.
- *   ranges     [T+1] int64: tile t owns sorted positions [ranges[t], ranges[t+1]).
- *   n_isect    int64 scalar: true intersection count (may exceed cap).
- *   grad2d     [M][9] float: per-pair 2D gradient sums (backward).
+ *   keys       [cap] uint32: sorted global tile ids, chunk after chunk.
+ *   vals       [cap] uint32: pair ids in (tile, depth, pair id) order within
+ *              each chunk.
+ *   ranges     [K][T+1] int64: in chunk c, tile t owns the sorted positions
+ *              chunk_base[c] + [ranges[c][t], ranges[c][t+1]).  A tile's list
+ *              is the concatenation of its chunk segments in chunk order.
+ *   n_isect    int64 scalar: intersection count of the complete lists.
+ *   chunk_base [K+1] int64: first entry of each chunk; chunk_base[K] is the
+ *              number of entries built.
+ *   chunk_n    [K] int64: entries of each chunk.
+ *   flags      int32[16]: flags[0] != 0 when the entries did not fit in the
+ *              capacity (the composite is then incomplete: grow the capacity
+ *              to at least n_isect and run again).
+ *   grad2d     [9][M] float: per-pair 2D gradient sums (backward), field-major.
  */
 typedef struct ls_layout {
-  int64_t n_pairs, n_tiles, n_pixels, capacity;
+  int64_t n_pairs, n_tiles, n_pixels, capacity, n_chunks;
   size_t total_bytes;
   size_t cams, proj, rect, ntiles, depth_key, order, isect_off, keys, vals, ranges,
-      n_isect, grad2d;
-  size_t scratch;   /* library-internal (sort buffers, histograms) */
+      n_isect, chunk_base, chunk_n, flags, grad2d;
+  size_t scratch;   /* library-internal (sort buffers, histograms, state) */
 } ls_layout;
 
 /* Library version (LSPLAT_VERSION). */
@@ -207,10 +227,12 @@ ls_status ls_project(const ls_config* cfg, const ls_splats* splats, const ls_cam
  * sort the entries by tile id, and compute each tile's range.  The result is
  * every tile's list in ascending (depth_key, pair id) order.  The paper keeps
  * this stage of the 3DGS pipeline (Sec. 3.2, Sec. 4.1) without describing it.
- * n_isect always receives the true count; when it exceeds the capacity,
- * nothing past the capacity is written, the sort is skipped and the
- * rasterizer calls of this workspace produce no output: read n_isect, grow
- * the capacity and run again.  Requires a preceding ls_project on `ws`.
+ * n_isect always receives the true count; when the entries do not fit in
+ * the capacity, nothing past the capacity is written, the lists stay empty
+ * and flags[0] is raised: grow the capacity and run again.  With
+ * depth_chunks > 1 this call stops after the depth order and the scan; the
+ * lists are built by ls_rasterize_fwd.  Requires a preceding ls_project on
+ * `ws`.
  */
 ls_status ls_bin_sort(const ls_config* cfg, const ls_cameras* cams, void* ws, size_t ws_bytes,
                       int64_t isect_capacity, void* stream);

@@ -50,6 +50,8 @@ static ls_status check_config(const ls_config* c) {
   if (!tile_shape_ok(c->tile_w, c->tile_h))
     return fail(LS_ERR_UNSUPPORTED, "tile shape %dx%d not supported (16x16, 16x8, 8x8, 32x8)",
                 c->tile_w, c->tile_h);
+  if (c->depth_chunks < 0 || c->depth_chunks > kMaxDepthChunks)
+    return fail(LS_ERR_INVALID_ARG, "depth_chunks must be 0..%d", kMaxDepthChunks);
   int pix = c->tile_w * c->tile_h;
   if (!(c->batch == 0 || c->batch == 64 || c->batch == 128 || c->batch == 256) || c->batch > pix)
     return fail(LS_ERR_INVALID_ARG, "batch must be 0, 64, 128 or 256 and at most the tile's pixels");
@@ -65,7 +67,7 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   if (!cams->h_width || !cams->h_height || !cams->h_scene_of_cam || !cams->h_scene_splat_off)
     return fail(LS_ERR_INVALID_ARG, "camera host arrays must not be NULL");
   if (cap < 0) return fail(LS_ERR_INVALID_ARG, "isect_capacity must be >= 0");
-  if (cap > (int64_t)0xFFFFFFFFll * 8) return fail(LS_ERR_INVALID_ARG, "isect_capacity too large");
+  if (cap >= (int64_t)0xFFFFFFFFll) return fail(LS_ERR_INVALID_ARG, "isect_capacity must be < 2^32 - 1");
   const int64_t* so = cams->h_scene_splat_off;
   if (so[0] != 0) return fail(LS_ERR_INVALID_ARG, "scene_splat_off[0] must be 0");
   for (int s = 0; s < cams->n_scenes; ++s)
@@ -101,6 +103,10 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   int bits = 0;
   while (bits < 32 && ((p->T - 1) >> bits) > 0) ++bits;
   p->tile_bits = bits;
+  // depth chunks: geometric boundaries M/2^(K-1), ..., M/2, M
+  p->K = cfg->depth_chunks < 1 ? 1 : cfg->depth_chunks;
+  p->chunk_pos.assign(p->K + 1, 0);
+  for (int c = 1; c <= p->K; ++c) p->chunk_pos[c] = p->M >> (p->K - c);
 
   // workspace layout
   size_t off = 0;
@@ -118,11 +124,15 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   L.isect_off = take(8 * (M + 1));
   L.keys = take(4 * CAP);
   L.vals = take(4 * CAP);
-  L.ranges = take(8 * (T + 1));
+  const size_t K = (size_t)p->K;
+  L.n_chunks = p->K;
+  L.ranges = take(8 * K * (T + 1));
   L.n_isect = take(8);
+  L.chunk_base = take(8 * (K + 1));
+  L.chunk_n = take(8 * K);
+  L.flags = take(64);
   L.grad2d = take(4 * kGrad2d * M);
   L.scratch = off;
-  p->flags = take(64);
   p->pre_keys_a = take(4 * M);
   p->pre_keys_b = take(4 * M);
   p->pre_vals_a = take(4 * M);
@@ -141,8 +151,16 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   int64_t sb = (p->M + 1 + kScanThreads * 16 - 1) / (kScanThreads * 16);
   p->scan_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(sb, kMaxScanBlocks));
   p->scan_part = take(8 * (size_t)(p->scan_blocks + 1));
-  p->n_spans = (cap + kKeygenSpan - 1) / kKeygenSpan + 1;
+  p->n_spans = (std::max<int64_t>(cap, 1) + kKeygenSpan - 1) / kKeygenSpan + 1;
   p->span_owner = take(4 * (size_t)p->n_spans);
+  p->span_cnt = take(4 * (size_t)p->n_spans);
+  p->span_off = take(4 * (size_t)p->n_spans);
+  p->chunk_spans = take(8 * K);
+  p->alive = take(4 * T);
+  if (p->K > 1) {
+    p->state = take(32 * (size_t)p->P);
+    p->done = take((size_t)p->P);
+  }
   L.total_bytes = off;
   return LS_OK;
 }

@@ -1,11 +1,13 @@
-// Binning: (tile, depth) ordering of all (tile, splat) intersections.
+// Binning: (tile, depth) ordering of the (tile, splat) intersections.
 //
 // Decomposition (an LSD radix sort split at the duplication step):
 //   1. depth presort   stable LSD radix sort of the M (camera, splat) pairs by
 //                      their 32-bit depth key; ties keep pair order.  Culled
 //                      pairs carry key 0xFFFFFFFF and land at the end.
 //   2. scan            exclusive scan (int64) of tiles-touched in that order;
-//                      the total is the intersection count.
+//                      the total is the intersection count.  The scan also
+//                      records which pair owns the first entry of every span
+//                      of kKeygenSpan output entries.
 //   3. keygen          one entry (global tile id, pair id) per touched tile,
 //                      written in depth order, load-balanced: each block owns
 //                      a fixed span of output entries, whatever the splat
@@ -19,10 +21,21 @@
 // the depth digits are sorted over M pairs instead of over the duplicated
 // entries.
 //
+// Depth chunks.  With K > 1 chunks, steps 3-5 run once per chunk of the
+// depth order (pair positions [pos_c, pos_c+1)), from the rasterizer, and a
+// chunk only emits entries for tiles that still have a pixel whose
+// transmittance has not run out.  Each tile's list is then the concatenation
+// of its chunk segments: a prefix of the complete list that holds every entry
+// the composite can reach.  Entries of a chunk are compacted in order
+// (count, scan, write), so the chunk's list is still exactly in (tile, depth,
+// pair id) order.
+//
 // Radix passes: 8-bit digits, reduce-then-scan with a fixed grid of G blocks
 // (each owning a contiguous span, so the order is stable), 256 threads per
 // block, 4096-key tiles; wave64 ballot matching ranks keys inside a wave,
 // LDS staging turns the scatter into runs of consecutive addresses per digit.
+// Counts and bases may live in device memory, so no launch shape depends on
+// a value the host has not seen.
 #include <algorithm>
 
 #include "internal.h"
@@ -34,12 +47,9 @@ namespace {
 constexpr int kKeygenThreads = 256;
 constexpr int kKeygenBlocks = 4096;
 constexpr int kRangeThreads = 256;
+constexpr int kScanBlocksMax = kMaxScanBlocks;
 
-__device__ __forceinline__ int64_t effective_n(const int64_t* n_dev, int64_t n_host, int64_t cap) {
-  if (!n_dev) return n_host;
-  int64_t n = *n_dev;
-  return (n <= cap) ? n : 0;   // on overflow nothing is sorted
-}
+__device__ __forceinline__ int64_t dev_or(const int64_t* p, int64_t v) { return p ? *p : v; }
 
 __device__ __forceinline__ void block_span(int64_t n, int G, int64_t* beg, int64_t* end) {
   int64_t tiles = (n + kSortTile - 1) / kSortTile;
@@ -74,20 +84,33 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_
   return wbase + x - v;
 }
 
+// ---------------------------------------------------------------------------
+// Radix sort passes over [base, base + n) of the key/value arrays.
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep(const uint32_t* __restrict__ keys,
+                                                              const int64_t* base_dev,
                                                               const int64_t* n_dev, int64_t n_host,
-                                                              int64_t cap, int shift, int G,
+                                                              int shift, int G,
                                                               uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[4][256];
   int tid = threadIdx.x, wave = tid >> 6;
   for (int i = tid; i < 4 * 256; i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
-  int64_t n = effective_n(n_dev, n_host, cap);
+  keys += dev_or(base_dev, 0);
+  const int64_t n = dev_or(n_dev, n_host);
   int64_t beg, end;
   block_span(n, G, &beg, &end);
-  for (int64_t i = beg + tid; i < end; i += kSortThreads) {
-    uint32_t d = (keys[i] >> shift) & 255u;
-    atomicAdd(&h[wave][d], 1u);
+  // 16 independent loads in flight per thread per iteration
+  for (int64_t tb = beg; tb < end; tb += kSortTile) {
+    uint32_t k[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const int64_t i = tb + j * kSortThreads + tid;
+      k[j] = i < end ? keys[i] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j)
+      if (tb + j * kSortThreads + tid < end) atomicAdd(&h[wave][(k[j] >> shift) & 255u], 1u);
   }
   __syncthreads();
   uint32_t s = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
@@ -124,8 +147,8 @@ __global__ __launch_bounds__(256) void radix_scan_rows(uint32_t* __restrict__ hi
 template <bool kIdentVals, bool kWriteKeys>
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, const int64_t* n_dev,
-    int64_t n_host, int64_t cap, int shift, int G, const uint32_t* __restrict__ hist,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, const int64_t* base_dev,
+    const int64_t* n_dev, int64_t n_host, int shift, int G, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_wcnt[4][256];
@@ -134,7 +157,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_vals[kSortTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int64_t n = effective_n(n_dev, n_host, cap);
+  const int64_t base_off = dev_or(base_dev, 0);
+  keys_in += base_off;
+  if (!kIdentVals) vals_in += base_off;
+  if (kWriteKeys) keys_out += base_off;
+  vals_out += base_off;
+  const int64_t n = dev_or(n_dev, n_host);
   int64_t beg, end;
   block_span(n, G, &beg, &end);
   // running global base of each digit for this block
@@ -143,7 +171,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
     uint32_t ex = block_excl_scan_256(t, s_tmp, nullptr);
     s_base[tid] = ex + hist[(int64_t)tid * G + blockIdx.x];
   }
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t tb = beg; tb < end; tb += kSortTile) {
     const int cnt = (int)((end - tb) < kSortTile ? (end - tb) : kSortTile);
 #pragma unroll
@@ -166,7 +193,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
         const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
         m &= bit ? bb : ~bb;
       }
-      const uint32_t pre = (uint32_t)__popcll(m & lt_mask);
+      // lanes below this one with the same digit
+      const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       uint32_t base = 0;
       if (valid) base = s_wcnt[wave][d];
       if (valid && pre == 0) s_wcnt[wave][d] = base + (uint32_t)__popcll(m);
@@ -215,30 +244,44 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of ntiles[order[p]] over p in [0, M) into int64 isect_off.
+// Three-kernel exclusive scan (per-block sums, one block scans the sums, each
+// block rescans its span) over inputs given by an accessor.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void scan_span(int64_t M, int B, int64_t* beg, int64_t* end) {
+struct PairCount {          // tiles touched by the pair at depth position p
+  const uint32_t* order;
+  const uint32_t* ntiles;
+  int64_t M;
+  __device__ int64_t operator()(int64_t p) const {
+    const uint32_t m = order[p];
+    return (m < (uint64_t)M) ? (int64_t)ntiles[m] : 0;
+  }
+};
+
+struct SpanCount {
+  const uint32_t* cnt;
+  __device__ int64_t operator()(int64_t s) const { return (int64_t)cnt[s]; }
+};
+
+__device__ __forceinline__ void scan_span(int64_t n, int B, int64_t* beg, int64_t* end) {
   const int64_t unit = kScanThreads * 16;
-  int64_t units = (M + unit - 1) / unit;
+  int64_t units = (n + unit - 1) / unit;
   int64_t per = (units + B - 1) / B;
   int64_t b = (int64_t)blockIdx.x * per * unit;
-  *beg = b < M ? b : M;
+  *beg = b < n ? b : n;
   int64_t e = b + per * unit;
-  *end = e < M ? e : M;
+  *end = e < n ? e : n;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_reduce(const uint32_t* __restrict__ order,
-                                                            const uint32_t* __restrict__ ntiles,
-                                                            int64_t M, int B,
+template <class In>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce(In in, const int64_t* n_dev,
+                                                            int64_t n_host, int B,
                                                             int64_t* __restrict__ part) {
   __shared__ int64_t s[kScanThreads / 64];
+  const int64_t n = dev_or(n_dev, n_host);
   int64_t beg, end;
-  scan_span(M, B, &beg, &end);
+  scan_span(n, B, &beg, &end);
   int64_t acc = 0;
-  for (int64_t p = beg + threadIdx.x; p < end; p += kScanThreads) {
-    const uint32_t m = order[p];
-    acc += (m < (uint64_t)M) ? ntiles[m] : 0u;
-  }
+  for (int64_t p = beg + threadIdx.x; p < end; p += kScanThreads) acc += in(p);
   for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -249,35 +292,63 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce(const uint32_t* __re
   }
 }
 
-__global__ void scan_parts(int64_t* __restrict__ part, int B, int64_t M,
-                           int64_t* __restrict__ isect_off, int64_t* __restrict__ n_isect) {
-  if (threadIdx.x != 0) return;
-  int64_t run = 0;
-  for (int b = 0; b < B; ++b) {
-    int64_t v = part[b];
-    part[b] = run;
-    run += v;
+// exclusive scan of part[0..B) in place (B <= 1024); part[B] = total
+__global__ __launch_bounds__(1024) void scan_parts(int64_t* __restrict__ part, int B) {
+  __shared__ int64_t s_w[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t v = tid < B ? part[tid] : 0;
+  int64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
   }
-  isect_off[M] = run;
-  *n_isect = run;
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  int64_t wbase = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) wbase += s_w[w];
+    tot += s_w[w];
+  }
+  if (tid < B) part[tid] = wbase + x - v;
+  if (tid == 0) part[B] = tot;
 }
 
-// Also records, for every key-generation span of kKeygenSpan output entries,
-// the pair that owns the span's first entry (span_owner[s]); the entry past
-// the last span names the last pair with entries.
-__global__ __launch_bounds__(kScanThreads) void scan_down(const uint32_t* __restrict__ order,
-                                                          const uint32_t* __restrict__ ntiles,
-                                                          int64_t M, int B,
-                                                          const int64_t* __restrict__ part,
-                                                          int64_t* __restrict__ isect_off,
-                                                          const int64_t* __restrict__ n_isect,
-                                                          uint32_t* __restrict__ span_owner,
-                                                          int64_t n_spans) {
-  const int64_t n_total = *n_isect;
+// pair scan output: offsets, and the owner pair of every keygen span
+struct PairOffsets {
+  int64_t* isect_off;
+  uint32_t* span_owner;
+  int64_t n_spans;
+  const int64_t* total;   // part[B]
+  __device__ void operator()(int64_t p, int64_t base, int64_t v) const {
+    isect_off[p] = base;
+    if (v > 0) {
+      for (int64_t sp = (base + kKeygenSpan - 1) / kKeygenSpan;
+           sp * kKeygenSpan < base + v && sp < n_spans; ++sp)
+        span_owner[sp] = (uint32_t)p;
+      const int64_t n_total = *total;
+      if (base + v == n_total) {
+        const int64_t term = (n_total + kKeygenSpan - 1) / kKeygenSpan;
+        if (term < n_spans) span_owner[term] = (uint32_t)p;
+      }
+    }
+  }
+};
+
+struct SpanOffsets {
+  uint32_t* off;
+  __device__ void operator()(int64_t s, int64_t base, int64_t) const { off[s] = (uint32_t)base; }
+};
+
+template <class In, class Out>
+__global__ __launch_bounds__(kScanThreads) void scan_down(In in, Out out, const int64_t* n_dev,
+                                                          int64_t n_host, int B,
+                                                          const int64_t* __restrict__ part) {
   __shared__ int64_t s_w[kScanThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n = dev_or(n_dev, n_host);
   int64_t beg, end;
-  scan_span(M, B, &beg, &end);
+  scan_span(n, B, &beg, &end);
   int64_t run = part[blockIdx.x];
   constexpr int kPer = 16;
   for (int64_t tb = beg; tb < end; tb += kScanThreads * kPer) {
@@ -286,8 +357,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down(const uint32_t* __rest
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       int64_t p = tb + (int64_t)tid * kPer + k;
-      const uint32_t m = p < end ? order[p] : 0xFFFFFFFFu;
-      v[k] = (m < (uint64_t)M) ? (int64_t)ntiles[m] : 0;
+      v[k] = p < end ? in(p) : 0;
       sum += v[k];
     }
     int64_t x = sum;
@@ -308,36 +378,50 @@ __global__ __launch_bounds__(kScanThreads) void scan_down(const uint32_t* __rest
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       int64_t p = tb + (int64_t)tid * kPer + k;
-      if (p < end) {
-        isect_off[p] = base;
-        if (v[k] > 0) {
-          for (int64_t sp = (base + kKeygenSpan - 1) / kKeygenSpan;
-               sp * kKeygenSpan < base + v[k] && sp < n_spans; ++sp)
-            span_owner[sp] = (uint32_t)p;
-          if (base + v[k] == n_total) {
-            const int64_t term = (n_total + kKeygenSpan - 1) / kKeygenSpan;
-            if (term < n_spans) span_owner[term] = (uint32_t)p;
-          }
-        }
-      }
+      if (p < end) out(p, base, v[k]);
       base += v[k];
     }
     run += tot;
   }
 }
 
-// ---------------------------------------------------------------------------
-// Key generation.  Block iteration covers output entries [k0, k0 + span).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t n, int64_t x) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (a[mid] <= x) lo = mid + 1;
-    else hi = mid;
+// After the pair scan: total intersections, and (complete-list mode) the
+// single chunk's count clamped to the capacity.
+__global__ void pairs_finalize(const int64_t* __restrict__ total, int64_t M,
+                               int64_t* __restrict__ isect_off, int64_t* __restrict__ n_isect,
+                               int64_t* __restrict__ chunk_base, int64_t* __restrict__ chunk_n,
+                               int32_t* __restrict__ flags, int64_t cap, int full_lists) {
+  if (threadIdx.x != 0) return;
+  const int64_t n = *total;
+  isect_off[M] = n;
+  *n_isect = n;
+  chunk_base[0] = 0;
+  flags[0] = 0;
+  if (full_lists) {
+    const bool ok = n <= cap;
+    chunk_n[0] = ok ? n : 0;
+    chunk_base[1] = ok ? n : 0;
+    if (!ok) flags[0] = 1;
   }
-  return lo;
 }
+
+// ---------------------------------------------------------------------------
+// Key generation.  One block iteration covers the output entries of one span
+// [s * kKeygenSpan, (s + 1) * kKeygenSpan); every entry learns its pair from
+// an LDS max-scan of the pairs' start positions and its tile from its offset
+// inside the pair's tile rectangle.
+// ---------------------------------------------------------------------------
+struct SpanTables {
+  int32_t owner[kKeygenSpan];
+  int64_t off[kKeygenSpan];
+  uint32_t m[kKeygenSpan];
+  uint32_t gbase[kKeygenSpan];
+  uint32_t w[kKeygenSpan];
+  uint32_t gx[kKeygenSpan];
+  int64_t plo, phi;
+  int32_t wmax[kKeygenThreads / 64];
+  int32_t wcnt[kKeygenThreads / 64];
+};
 
 __device__ __forceinline__ int cam_of_pair(const CamInfo* cams, int C, int64_t m) {
   int lo = 0, hi = C - 1;
@@ -349,102 +433,197 @@ __device__ __forceinline__ int cam_of_pair(const CamInfo* cams, int C, int64_t m
   return lo;
 }
 
+// Fill the tables for span s (entries k0 = s * span ...).  Block-uniform.
+__device__ __forceinline__ void span_setup(SpanTables& t, int64_t s,
+                                           const uint32_t* __restrict__ order,
+                                           const int64_t* __restrict__ isect_off,
+                                           const ushort4* __restrict__ rect,
+                                           const CamInfo* __restrict__ cams, int C, int64_t M,
+                                           const uint32_t* __restrict__ span_owner) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t k0 = s * kKeygenSpan;
+  if (tid == 0) {
+    int64_t lo = span_owner[s], hi = span_owner[s + 1];
+    if (lo > M - 1) lo = M - 1;
+    if (hi > M - 1) hi = M - 1;
+    if (hi < lo) hi = lo;
+    t.plo = lo;
+    t.phi = hi;
+  }
+  for (int i = tid; i < kKeygenSpan; i += kKeygenThreads) t.owner[i] = 0;
+  __syncthreads();
+  const int64_t plo = t.plo, phi = t.phi;
+  for (int64_t p = plo + tid; p <= phi && p - plo < kKeygenSpan; p += kKeygenThreads) {
+    const int pl = (int)(p - plo);
+    const int64_t off = isect_off[p];
+    uint32_t m = order[p];
+    if (m >= (uint64_t)M) m = 0;   // unreachable for a valid order
+    const ushort4 rc = rect[m];
+    const int c = cam_of_pair(cams, C, (int64_t)m);
+    const CamInfo& ci = cams[c];
+    t.off[pl] = off;
+    t.m[pl] = m;
+    t.gbase[pl] = (uint32_t)(ci.tile_off + (int64_t)rc.y * ci.GX + rc.x);
+    t.w[pl] = (uint32_t)(rc.z - rc.x + 1);
+    t.gx[pl] = (uint32_t)ci.GX;
+    if (p > plo && off > k0 && off < k0 + kKeygenSpan) t.owner[(int)(off - k0)] = pl;
+  }
+  __syncthreads();
+  // inclusive max-scan of owner: each entry learns its pair
+  constexpr int kPer = kKeygenSpan / kKeygenThreads;
+  int32_t loc[kPer];
+  int32_t mx = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    int32_t o = t.owner[tid * kPer + k];
+    mx = o > mx ? o : mx;
+    loc[k] = mx;
+  }
+  int32_t x = mx;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x = y > x ? y : x;
+  }
+  if (lane == 63) t.wmax[wave] = x;
+  int32_t ex = __shfl_up(x, 1, 64);
+  if (lane == 0) ex = 0;
+  __syncthreads();
+  int32_t wpre = 0;
+  for (int w = 0; w < wave; ++w) wpre = t.wmax[w] > wpre ? t.wmax[w] : wpre;
+  ex = ex > wpre ? ex : wpre;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) t.owner[tid * kPer + k] = loc[k] > ex ? loc[k] : ex;
+  __syncthreads();
+}
+
+// global tile id and pair id of entry k0 + i
+__device__ __forceinline__ void span_entry(const SpanTables& t, int64_t k0, int i,
+                                           uint32_t* gtile, uint32_t* m) {
+  const int pl = t.owner[i];
+  const uint32_t local = (uint32_t)(k0 + i - t.off[pl]);
+  const uint32_t w = t.w[pl];
+  // local / w with a float estimate corrected to the exact quotient
+  uint32_t ty = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)w));
+  int32_t rem = (int32_t)local - (int32_t)(ty * w);
+  while (rem < 0) { --ty; rem += (int32_t)w; }
+  while (rem >= (int32_t)w) { ++ty; rem -= (int32_t)w; }
+  *gtile = t.gbase[pl] + ty * t.gx[pl] + (uint32_t)rem;
+  *m = t.m[pl];
+}
+
+// complete lists: every entry, at its own index
 __global__ __launch_bounds__(kKeygenThreads) void keygen_kernel(
     const uint32_t* __restrict__ order, const int64_t* __restrict__ isect_off,
     const ushort4* __restrict__ rect, const CamInfo* __restrict__ cams, int C, int64_t M,
-    const int64_t* __restrict__ n_isect, int64_t cap, const uint32_t* __restrict__ span_owner,
+    const int64_t* __restrict__ n_dev, const uint32_t* __restrict__ span_owner,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ int32_t s_owner[kKeygenSpan];
-  __shared__ int64_t s_off[kKeygenSpan];
-  __shared__ uint32_t s_m[kKeygenSpan];
-  __shared__ uint32_t s_gbase[kKeygenSpan];
-  __shared__ uint32_t s_w[kKeygenSpan];
-  __shared__ uint32_t s_gx[kKeygenSpan];
-  __shared__ int64_t s_plo, s_phi;
-  __shared__ int32_t s_wmax[kKeygenThreads / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t n = *n_isect;
-  if (n > cap) return;
-  for (int64_t k0 = (int64_t)blockIdx.x * kKeygenSpan; k0 < n; k0 += (int64_t)gridDim.x * kKeygenSpan) {
-    const int64_t k1 = (k0 + kKeygenSpan < n) ? k0 + kKeygenSpan : n;
-    if (tid == 0) {
-      const int64_t sp = k0 / kKeygenSpan;
-      int64_t lo = span_owner[sp], hi = span_owner[sp + 1];
-      if (lo > M - 1) lo = M - 1;
-      if (hi > M - 1) hi = M - 1;
-      if (hi < lo) hi = lo;
-      s_plo = lo;
-      s_phi = hi;
-    }
-    for (int i = tid; i < kKeygenSpan; i += kKeygenThreads) s_owner[i] = 0;
-    __syncthreads();
-    const int64_t plo = s_plo, phi = s_phi;
-    // per-pair data of every pair owning entries of this span
-    for (int64_t p = plo + tid; p <= phi && p - plo < kKeygenSpan; p += kKeygenThreads) {
-      const int pl = (int)(p - plo);
-      const int64_t off = isect_off[p];
-      uint32_t m = order[p];
-      if (m >= (uint64_t)M) m = 0;   // unreachable for a valid order
-      const ushort4 rc = rect[m];
-      const int c = cam_of_pair(cams, C, (int64_t)m);
-      const CamInfo& ci = cams[c];
-      s_off[pl] = off;
-      s_m[pl] = m;
-      s_gbase[pl] = (uint32_t)(ci.tile_off + (int64_t)rc.y * ci.GX + rc.x);
-      s_w[pl] = (uint32_t)(rc.z - rc.x + 1);
-      s_gx[pl] = (uint32_t)ci.GX;
-      if (p > plo && off > k0 && off < k0 + kKeygenSpan) s_owner[(int)(off - k0)] = pl;
-    }
-    __syncthreads();
-    // inclusive max-scan of s_owner: each entry learns its pair
-    constexpr int kPer = kKeygenSpan / kKeygenThreads;
-    int32_t loc[kPer];
-    int32_t mx = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      int32_t o = s_owner[tid * kPer + k];
-      mx = o > mx ? o : mx;
-      loc[k] = mx;
-    }
-    int32_t x = mx;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      int32_t y = __shfl_up(x, d, 64);
-      if (lane >= d) x = y > x ? y : x;
-    }
-    if (lane == 63) s_wmax[wave] = x;
-    int32_t ex = __shfl_up(x, 1, 64);
-    if (lane == 0) ex = 0;
-    __syncthreads();
-    int32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre = s_wmax[w] > wpre ? s_wmax[w] : wpre;
-    ex = ex > wpre ? ex : wpre;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) s_owner[tid * kPer + k] = loc[k] > ex ? loc[k] : ex;
-    __syncthreads();
-    for (int i = tid; i < (int)(k1 - k0); i += kKeygenThreads) {
-      const int pl = s_owner[i];
-      const uint32_t local = (uint32_t)(k0 + i - s_off[pl]);
-      const uint32_t w = s_w[pl];
-      // local / w with a float estimate corrected to the exact quotient
-      uint32_t ty = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)w));
-      int32_t rem = (int32_t)local - (int32_t)(ty * w);
-      while (rem < 0) { --ty; rem += (int32_t)w; }
-      while (rem >= (int32_t)w) { ++ty; rem -= (int32_t)w; }
-      keys[k0 + i] = s_gbase[pl] + ty * s_gx[pl] + (uint32_t)rem;
-      vals[k0 + i] = s_m[pl];
+  __shared__ SpanTables t;
+  const int64_t n = *n_dev;
+  for (int64_t s = blockIdx.x; s * kKeygenSpan < n; s += gridDim.x) {
+    span_setup(t, s, order, isect_off, rect, cams, C, M, span_owner);
+    const int64_t k0 = s * kKeygenSpan;
+    const int cnt = (int)((n - k0) < kKeygenSpan ? (n - k0) : kKeygenSpan);
+    for (int i = threadIdx.x; i < cnt; i += kKeygenThreads) {
+      uint32_t g, m;
+      span_entry(t, k0, i, &g, &m);
+      keys[k0 + i] = g;
+      vals[k0 + i] = m;
     }
     __syncthreads();
   }
 }
 
-// ranges[t] = number of sorted keys < t, for t in [0, T]
+// Chunk c of the depth order: entries [E_c, E_c1) with E = isect_off[pos].
+// kCount: per-span count of entries whose tile is alive.
+// !kCount: write those entries, in order, at base + span_off[span].
+template <bool kCount>
+__global__ __launch_bounds__(kKeygenThreads) void keygen_chunk_kernel(
+    const uint32_t* __restrict__ order, const int64_t* __restrict__ isect_off,
+    const ushort4* __restrict__ rect, const CamInfo* __restrict__ cams, int C, int64_t M,
+    int64_t pos_lo, int64_t pos_hi, const uint32_t* __restrict__ span_owner,
+    const uint32_t* __restrict__ alive, uint32_t* __restrict__ span_cnt,
+    int64_t* __restrict__ n_spans_out, const uint32_t* __restrict__ span_off,
+    const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ SpanTables t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t E0 = isect_off[pos_lo], E1 = isect_off[pos_hi];
+  const int64_t s0 = E0 / kKeygenSpan;
+  const int64_t s1 = (E1 > E0) ? (E1 + kKeygenSpan - 1) / kKeygenSpan : s0;
+  if (kCount && blockIdx.x == 0 && tid == 0) *n_spans_out = s1 - s0;
+  int64_t base = 0;
+  if (!kCount) {
+    if (*chunk_n == 0) return;    // empty chunk or capacity overflow
+    base = *chunk_base;
+  }
+  for (int64_t s = s0 + blockIdx.x; s < s1; s += gridDim.x) {
+    span_setup(t, s, order, isect_off, rect, cams, C, M, span_owner);
+    const int64_t k0 = s * kKeygenSpan;
+    uint32_t run = 0;
+    const uint32_t out0 = kCount ? 0u : span_off[s - s0];
+    for (int r = 0; r < kKeygenSpan; r += kKeygenThreads) {
+      const int64_t k = k0 + r + tid;
+      bool keep = false;
+      uint32_t g = 0, m = 0;
+      if (k >= E0 && k < E1) {
+        span_entry(t, k0, r + tid, &g, &m);
+        keep = alive[g] != 0u;
+      }
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
+      if (lane == 0) t.wcnt[wave] = (int32_t)__popcll(bal);
+      __syncthreads();
+      uint32_t wbase = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < kKeygenThreads / 64; ++w) {
+        const uint32_t c = (uint32_t)t.wcnt[w];
+        wbase += (w < wave) ? c : 0u;
+        tot += c;
+      }
+      if (!kCount && keep) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        const int64_t dst = base + out0 + run + wbase + rank;
+        keys[dst] = g;
+        vals[dst] = m;
+      }
+      run += tot;
+      __syncthreads();
+    }
+    if (kCount && tid == 0) span_cnt[s - s0] = run;
+    __syncthreads();
+  }
+}
+
+// After the span-count scan of chunk c: the chunk's entry count, its base and
+// the capacity check.  A chunk that would overflow is dropped (count 0) and
+// the overflow flag raised; later chunks then see no room either.
+__global__ void chunk_finalize(const int64_t* __restrict__ total, int64_t* __restrict__ chunk_base,
+                               int64_t* __restrict__ chunk_n, int32_t* __restrict__ flags,
+                               int64_t cap) {
+  if (threadIdx.x != 0) return;
+  const int64_t n = *total;
+  const int64_t b = chunk_base[0];
+  const bool ok = flags[0] == 0 && b + n <= cap;
+  chunk_n[0] = ok ? n : 0;
+  chunk_base[1] = ok ? b + n : b;
+  if (!ok && n > 0) flags[0] = 1;
+}
+
+__global__ void chunk_empty(int64_t* __restrict__ chunk_base, int64_t* __restrict__ chunk_n) {
+  if (threadIdx.x != 0) return;
+  chunk_n[0] = 0;
+  chunk_base[1] = chunk_base[0];
+}
+
+// ranges[t] = number of sorted keys < t among keys[base, base + n), t in [0, T]
 __global__ __launch_bounds__(kRangeThreads) void ranges_kernel(const uint32_t* __restrict__ keys,
-                                                               const int64_t* __restrict__ n_isect,
-                                                               int64_t cap, int64_t T,
+                                                               const int64_t* __restrict__ base_dev,
+                                                               const int64_t* __restrict__ n_dev,
+                                                               int64_t T,
                                                                int64_t* __restrict__ ranges) {
-  int64_t n = *n_isect;
-  if (n > cap) n = 0;
+  const int64_t n = *n_dev;
+  keys += *base_dev;
   for (int64_t t = (int64_t)blockIdx.x * kRangeThreads + threadIdx.x; t <= T;
        t += (int64_t)gridDim.x * kRangeThreads) {
     int64_t lo = 0, hi = n;
@@ -457,19 +636,16 @@ __global__ __launch_bounds__(kRangeThreads) void ranges_kernel(const uint32_t* _
   }
 }
 
-struct SortBufs {
-  uint32_t *ka, *va, *kb, *vb;
-};
-
 // One LSD pass; returns the launch error.
 template <bool kIdent, bool kWriteKeys>
 hipError_t radix_pass(const char* const names[3], const uint32_t* kin, const uint32_t* vin,
-                      uint32_t* kout, uint32_t* vout, const int64_t* n_dev, int64_t n_host,
-                      int64_t cap, int shift, int G, uint32_t* hist, uint32_t* tot, hipStream_t s) {
+                      uint32_t* kout, uint32_t* vout, const int64_t* base_dev,
+                      const int64_t* n_dev, int64_t n_host, int shift, int G, uint32_t* hist,
+                      uint32_t* tot, hipStream_t s) {
   {
     ProfScope ps(names[0], s);
-    hipLaunchKernelGGL(radix_upsweep, dim3(G), dim3(kSortThreads), 0, s, kin, n_dev, n_host, cap,
-                       shift, G, hist);
+    hipLaunchKernelGGL(radix_upsweep, dim3(G), dim3(kSortThreads), 0, s, kin, base_dev, n_dev,
+                       n_host, shift, G, hist);
   }
   {
     ProfScope ps(names[1], s);
@@ -478,13 +654,53 @@ hipError_t radix_pass(const char* const names[3], const uint32_t* kin, const uin
   {
     ProfScope ps(names[2], s);
     hipLaunchKernelGGL((radix_downsweep<kIdent, kWriteKeys>), dim3(G), dim3(kSortThreads), 0, s,
-                       kin, vin, kout, vout, n_dev, n_host, cap, shift, G, hist, tot);
+                       kin, vin, kout, vout, base_dev, n_dev, n_host, shift, G, hist, tot);
   }
   return hipGetLastError();
 }
 
 const char* const kPreNames[3] = {"presort_upsweep", "presort_scan", "presort_downsweep"};
 const char* const kTileNames[3] = {"tilesort_upsweep", "tilesort_scan", "tilesort_downsweep"};
+
+int scan_blocks_for(int64_t n) {
+  int64_t b = (n + kScanThreads * 16 - 1) / (kScanThreads * 16);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, kScanBlocksMax));
+}
+
+// Sort the entries [base, base + n) of (keys, vals) by tile id, then ranges.
+hipError_t tile_sort_and_ranges(const Plan& p, char* ws, const int64_t* base_dev,
+                                const int64_t* n_dev, int64_t* ranges_out, hipStream_t s) {
+  hipError_t e;
+  const int passes = (p.tile_bits + 7) / 8;
+  uint32_t* kA = (uint32_t*)(ws + p.lay.keys);
+  uint32_t* vA = (uint32_t*)(ws + p.lay.vals);
+  uint32_t* kB = (uint32_t*)(ws + p.sort_keys_b);
+  uint32_t* vB = (uint32_t*)(ws + p.sort_vals_b);
+  uint32_t* hist = (uint32_t*)(ws + p.hist);
+  uint32_t* tot = (uint32_t*)(ws + p.digit_tot);
+  uint32_t *kin = (passes % 2 == 0) ? kA : kB, *vin = (passes % 2 == 0) ? vA : vB;
+  for (int pass = 0; pass < passes; ++pass) {
+    uint32_t* kout = (kin == kA) ? kB : kA;
+    uint32_t* vout = (vin == vA) ? vB : vA;
+    if ((e = radix_pass<false, true>(kTileNames, kin, vin, kout, vout, base_dev, n_dev, 0,
+                                     8 * pass, p.sort_blocks, hist, tot, s)))
+      return e;
+    kin = kout;
+    vin = vout;
+  }
+  int64_t blocks = std::min<int64_t>((p.T + 1 + kRangeThreads - 1) / kRangeThreads, 4096);
+  ProfScope ps("ranges", s);
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(kRangeThreads), 0, s, kA,
+                     base_dev, n_dev, p.T, ranges_out);
+  return hipGetLastError();
+}
+
+// The buffer the key generation writes to, so that the sort ends in (keys, vals).
+void keygen_targets(const Plan& p, char* ws, uint32_t** k0, uint32_t** v0) {
+  const int passes = (p.tile_bits + 7) / 8;
+  *k0 = (uint32_t*)(ws + ((passes % 2 == 0) ? p.lay.keys : p.sort_keys_b));
+  *v0 = (uint32_t*)(ws + ((passes % 2 == 0) ? p.lay.vals : p.sort_vals_b));
+}
 
 }  // namespace
 
@@ -499,6 +715,9 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
   uint32_t* order = (uint32_t*)(ws + p.lay.order);
   const uint32_t* ntiles = (const uint32_t*)(ws + p.lay.ntiles);
   const uint32_t* dkey = (const uint32_t*)(ws + p.lay.depth_key);
+  int64_t* chunk_base = (int64_t*)(ws + p.lay.chunk_base);
+  int64_t* chunk_n = (int64_t*)(ws + p.lay.chunk_n);
+  int32_t* flags = (int32_t*)(ws + p.lay.flags);
 
   // 1. depth presort of the M pairs: 4 passes of 8 bits
   if (M > 0) {
@@ -507,68 +726,108 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
     uint32_t* kB = (uint32_t*)(ws + p.pre_keys_b);
     uint32_t* vB = (uint32_t*)(ws + p.pre_vals_b);
     const int G = p.pre_blocks;
-    if ((e = radix_pass<true, true>(kPreNames, dkey, nullptr, kB, vB, nullptr, M, M, 0, G, hist, tot, s))) return e;
-    if ((e = radix_pass<false, true>(kPreNames, kB, vB, kA, vA, nullptr, M, M, 8, G, hist, tot, s))) return e;
-    if ((e = radix_pass<false, true>(kPreNames, kA, vA, kB, vB, nullptr, M, M, 16, G, hist, tot, s))) return e;
-    if ((e = radix_pass<false, false>(kPreNames, kB, vB, nullptr, order, nullptr, M, M, 24, G, hist, tot, s)))
+    if ((e = radix_pass<true, true>(kPreNames, dkey, nullptr, kB, vB, nullptr, nullptr, M, 0, G,
+                                    hist, tot, s)))
+      return e;
+    if ((e = radix_pass<false, true>(kPreNames, kB, vB, kA, vA, nullptr, nullptr, M, 8, G, hist,
+                                     tot, s)))
+      return e;
+    if ((e = radix_pass<false, true>(kPreNames, kA, vA, kB, vB, nullptr, nullptr, M, 16, G, hist,
+                                     tot, s)))
+      return e;
+    if ((e = radix_pass<false, false>(kPreNames, kB, vB, nullptr, order, nullptr, nullptr, M, 24,
+                                      G, hist, tot, s)))
       return e;
   }
-  // 2. scan of tile counts in depth order
+  // 2. scan of tile counts in depth order (+ span owners)
   {
     int64_t* part = (int64_t*)(ws + p.scan_part);
-    const int B = p.scan_blocks;
+    const int B = scan_blocks_for(M);
+    PairCount in{order, ntiles, M};
+    PairOffsets out{isect_off, (uint32_t*)(ws + p.span_owner), p.n_spans, part + B};
     ProfScope ps("scan", s);
-    if (M > 0) {
-      hipLaunchKernelGGL(scan_reduce, dim3(B), dim3(kScanThreads), 0, s, order, ntiles, M, B, part);
-    }
-    hipLaunchKernelGGL(scan_parts, dim3(1), dim3(64), 0, s, part, M > 0 ? B : 0, M, isect_off,
-                       n_isect);
-    if (M > 0) {
-      hipLaunchKernelGGL(scan_down, dim3(B), dim3(kScanThreads), 0, s, order, ntiles, M, B, part,
-                         isect_off, n_isect, (uint32_t*)(ws + p.span_owner), p.n_spans);
-    }
+    hipLaunchKernelGGL(scan_reduce<PairCount>, dim3(B), dim3(kScanThreads), 0, s, in, nullptr, M,
+                       B, part);
+    hipLaunchKernelGGL(scan_parts, dim3(1), dim3(1024), 0, s, part, B);
+    hipLaunchKernelGGL((scan_down<PairCount, PairOffsets>), dim3(B), dim3(kScanThreads), 0, s, in,
+                       out, nullptr, M, B, part);
+    hipLaunchKernelGGL(pairs_finalize, dim3(1), dim3(64), 0, s, part + B, M, isect_off, n_isect,
+                       chunk_base, chunk_n, flags, p.cap, p.K == 1 ? 1 : 0);
     if ((e = hipGetLastError())) return e;
   }
-  // 3 + 4. key generation and the tile sort
-  int passes = (p.tile_bits + 7) / 8;
-  uint32_t* kA = (uint32_t*)(ws + p.lay.keys);
-  uint32_t* vA = (uint32_t*)(ws + p.lay.vals);
-  uint32_t* kB = (uint32_t*)(ws + p.sort_keys_b);
-  uint32_t* vB = (uint32_t*)(ws + p.sort_vals_b);
-  const CamInfo* cams = (const CamInfo*)(ws + p.lay.cams);
+  if (p.K > 1) return hipSuccess;   // lists are built chunk by chunk by the rasterizer
+  // 3 + 4 + 5. key generation, tile sort and ranges of the complete lists
   if (p.cap > 0 && M > 0) {
-    uint32_t* k0 = (passes % 2 == 0) ? kA : kB;
-    uint32_t* v0 = (passes % 2 == 0) ? vA : vB;
+    uint32_t *k0, *v0;
+    keygen_targets(p, ws, &k0, &v0);
     int64_t spans = (p.cap + kKeygenSpan - 1) / kKeygenSpan;
     int blocks = (int)std::min<int64_t>(spans, kKeygenBlocks);
     {
       ProfScope ps("keygen", s);
-      hipLaunchKernelGGL(keygen_kernel, dim3(blocks), dim3(kKeygenThreads), 0, s, order, isect_off,
-                         (const ushort4*)(ws + p.lay.rect), cams, p.C, M, n_isect, p.cap,
+      hipLaunchKernelGGL(keygen_kernel, dim3(blocks), dim3(kKeygenThreads), 0, s, order,
+                         isect_off, (const ushort4*)(ws + p.lay.rect),
+                         (const CamInfo*)(ws + p.lay.cams), p.C, M, chunk_n,
                          (const uint32_t*)(ws + p.span_owner), k0, v0);
     }
     if ((e = hipGetLastError())) return e;
-    const int G = p.sort_blocks;
-    uint32_t *kin = k0, *vin = v0;
-    for (int pass = 0; pass < passes; ++pass) {
-      uint32_t* kout = (kin == kA) ? kB : kA;
-      uint32_t* vout = (vin == vA) ? vB : vA;
-      if ((e = radix_pass<false, true>(kTileNames, kin, vin, kout, vout, n_isect, 0, p.cap, 8 * pass, G, hist,
-                                       tot, s)))
-        return e;
-      kin = kout;
-      vin = vout;
-    }
   }
-  // 5. ranges
-  {
-    int64_t blocks = std::min<int64_t>((p.T + 1 + kRangeThreads - 1) / kRangeThreads, 4096);
-    ProfScope ps("ranges", s);
-    hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(kRangeThreads), 0, s, kA, n_isect,
-                       p.cap, p.T, (int64_t*)(ws + p.lay.ranges));
+  return tile_sort_and_ranges(p, ws, chunk_base, chunk_n, (int64_t*)(ws + p.lay.ranges), s);
+}
+
+hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
+  hipError_t e;
+  const int64_t M = p.M;
+  int64_t* chunk_base = (int64_t*)(ws + p.lay.chunk_base) + c;
+  int64_t* chunk_n = (int64_t*)(ws + p.lay.chunk_n) + c;
+  if (M > 0 && p.cap > 0) {
+    const int64_t* isect_off = (const int64_t*)(ws + p.lay.isect_off);
+    const uint32_t* order = (const uint32_t*)(ws + p.lay.order);
+    int32_t* flags = (int32_t*)(ws + p.lay.flags);
+    uint32_t* span_cnt = (uint32_t*)(ws + p.span_cnt);
+    uint32_t* span_off = (uint32_t*)(ws + p.span_off);
+    int64_t* n_spans = (int64_t*)(ws + p.chunk_spans) + c;
+    const uint32_t* alive = (const uint32_t*)(ws + p.alive);
+    const int64_t lo = p.chunk_pos[c], hi = p.chunk_pos[c + 1];
+    const int blocks = (int)std::min<int64_t>(p.n_spans, kKeygenBlocks);
+    uint32_t *k0, *v0;
+    keygen_targets(p, ws, &k0, &v0);
+    {
+      ProfScope ps("keygen_count", s);
+      hipLaunchKernelGGL(keygen_chunk_kernel<true>, dim3(blocks), dim3(kKeygenThreads), 0, s,
+                         order, isect_off, (const ushort4*)(ws + p.lay.rect),
+                         (const CamInfo*)(ws + p.lay.cams), p.C, M, lo, hi,
+                         (const uint32_t*)(ws + p.span_owner), alive, span_cnt, n_spans, nullptr,
+                         nullptr, nullptr, nullptr, nullptr);
+    }
+    {
+      int64_t* part = (int64_t*)(ws + p.scan_part);
+      const int B = scan_blocks_for(p.n_spans);
+      SpanCount in{span_cnt};
+      SpanOffsets out{span_off};
+      ProfScope ps("chunk_scan", s);
+      hipLaunchKernelGGL(scan_reduce<SpanCount>, dim3(B), dim3(kScanThreads), 0, s, in, n_spans,
+                         0, B, part);
+      hipLaunchKernelGGL(scan_parts, dim3(1), dim3(1024), 0, s, part, B);
+      hipLaunchKernelGGL((scan_down<SpanCount, SpanOffsets>), dim3(B), dim3(kScanThreads), 0, s,
+                         in, out, n_spans, 0, B, part);
+      hipLaunchKernelGGL(chunk_finalize, dim3(1), dim3(64), 0, s, part + B, chunk_base, chunk_n,
+                         flags, p.cap);
+    }
+    {
+      ProfScope ps("keygen_write", s);
+      hipLaunchKernelGGL(keygen_chunk_kernel<false>, dim3(blocks), dim3(kKeygenThreads), 0, s,
+                         order, isect_off, (const ushort4*)(ws + p.lay.rect),
+                         (const CamInfo*)(ws + p.lay.cams), p.C, M, lo, hi,
+                         (const uint32_t*)(ws + p.span_owner), alive, nullptr, nullptr, span_off,
+                         chunk_base, chunk_n, k0, v0);
+    }
+    if ((e = hipGetLastError())) return e;
+  } else {
+    hipLaunchKernelGGL(chunk_empty, dim3(1), dim3(64), 0, s, chunk_base, chunk_n);
     if ((e = hipGetLastError())) return e;
   }
-  return hipSuccess;
+  return tile_sort_and_ranges(p, ws, chunk_base, chunk_n,
+                              (int64_t*)(ws + p.lay.ranges) + (int64_t)c * (p.T + 1), s);
 }
 
 }  // namespace lsplat

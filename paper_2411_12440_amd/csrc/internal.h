@@ -60,8 +60,11 @@ struct Plan {
   ls_layout lay{};
   // scratch sub-allocations (byte offsets from the workspace base)
   size_t sort_keys_b = 0, sort_vals_b = 0, pre_keys_a = 0, pre_keys_b = 0, pre_vals_a = 0, pre_vals_b = 0,
-         hist = 0, digit_tot = 0, scan_part = 0, flags = 0, span_owner = 0;
+         hist = 0, digit_tot = 0, scan_part = 0, span_owner = 0, span_cnt = 0, span_off = 0,
+         chunk_spans = 0, alive = 0, state = 0, done = 0;
   int64_t n_spans = 0;        // entries of span_owner: ceil(cap / kKeygenSpan) + 1
+  int32_t K = 1;              // depth chunks
+  std::vector<int64_t> chunk_pos;   // [K + 1] pair positions in depth order
   int32_t sort_blocks = 0;    // radix sort grid for the intersection sort
   int32_t pre_blocks = 0;     // radix sort grid for the depth presort
   int32_t scan_blocks = 0;
@@ -74,6 +77,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxSortBlocks = 1024;
 constexpr int kScanThreads = 256;
 constexpr int kKeygenSpan = 2048;   // output entries per key-generation block iteration
+constexpr int kMaxDepthChunks = 12;
 constexpr int kMaxScanBlocks = 1024;
 
 // ---------------------------------------------------------------------------
@@ -111,6 +115,7 @@ hipError_t launch_cam_setup(const Plan& p, const ls_cameras* cams, char* ws, hip
 hipError_t launch_project(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                           hipStream_t s);
 hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStream_t s);
+hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s);
 hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, float* image,
                              float* final_T, int32_t* last, hipStream_t s);
 hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,

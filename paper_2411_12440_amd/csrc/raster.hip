@@ -124,21 +124,22 @@ __device__ __forceinline__ bool ellipse_hits_rect(double ox, double oy, double A
   return best < lam2 * (1.0 + 1e-6);
 }
 
-// Stage list positions [p0, p0 + nb) of a tile whose list starts at `start`;
-// returns the number of surviving entries (block-uniform).
+// Stage one batch: thread i (i < NT) brings entry `vidx` of the sorted
+// values (if `has`), whose position in the tile's list is `gpos`.  Returns the
+// number of surviving entries (block-uniform).
 template <int TW, int TH>
 __device__ __forceinline__ int stage_batch(Stage<TW * TH>& st, const uint32_t* __restrict__ vals,
-                                           const ProjRec* __restrict__ proj, int64_t M,
-                                           int64_t start, int32_t p0, int nb, double x0c,
-                                           double y0c, double lam2) {
+                                           const ProjRec* __restrict__ proj, int64_t M, bool has,
+                                           int64_t vidx, int32_t gpos, double x0c, double y0c,
+                                           double lam2) {
   constexpr int NT = TW * TH;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool keep = false;
   uint32_t m = 0;
   ProjRec rec;
   double ox = 0.0, oy = 0.0;
-  if (tid < nb) {
-    m = vals[start + p0 + tid];
+  if (has) {
+    m = vals[vidx];
     if (m >= (uint64_t)M) m = 0;   // unreachable for a valid list
     rec = proj[m];
     ox = rec.mx - x0c;
@@ -156,8 +157,8 @@ __device__ __forceinline__ int stage_batch(Stage<TW * TH>& st, const uint32_t* _
     total += c;
   }
   if (keep) {
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int k = base + (int)__popcll(bal & lt);
+    const int k = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
     const double A = rec.A, B = rec.B, C = rec.C;
     const double u = A * ox + B * oy, v = B * ox + C * oy;
     st.qa[k] = A;
@@ -172,25 +173,39 @@ __device__ __forceinline__ int stage_batch(Stage<TW * TH>& st, const uint32_t* _
     st.g[k] = rec.g;
     st.b[k] = rec.b;
     st.o[k] = rec.o;
-    st.pos[k] = p0 + tid;
+    st.pos[k] = gpos;
     st.m[k] = m;
   }
   __syncthreads();
   return total;
 }
 
+// Forward composite of chunk c of K: each tile continues from the state its
+// pixels reached in the previous chunks (T and colour in FP64, the stop flag
+// and `last`) over its segment of this chunk's sorted list.
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
-    const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges,
-    const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
-    RasterParams rp, float* __restrict__ image, float* __restrict__ final_T,
-    int32_t* __restrict__ last) {
+    const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all, int64_t T_all,
+    int c, int K, const int64_t* __restrict__ chunk_base, const uint32_t* __restrict__ vals,
+    const ProjRec* __restrict__ proj, int64_t M, int batch, RasterParams rp,
+    double4* __restrict__ state, uint8_t* __restrict__ done_px, uint32_t* __restrict__ alive,
+    float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ last) {
   constexpr int NT = TW * TH;
   __shared__ Stage<NT> st;
   const int tid = threadIdx.x;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int c = cam_of_tile(cams, C, tile);
-  const CamInfo& ci = cams[c];
+  if (c > 0 && alive[tile] == 0u) return;
+  const int64_t* ranges = ranges_all + (int64_t)c * (T_all + 1);
+  const int32_t len = (int32_t)(ranges[tile + 1] - ranges[tile]);
+  if (c > 0 && len == 0) return;
+  const int64_t start = chunk_base[c] + ranges[tile];
+  int32_t prefix = 0;
+  for (int cc = 0; cc < c; ++cc) {
+    const int64_t* r = ranges_all + (int64_t)cc * (T_all + 1);
+    prefix += (int32_t)(r[tile + 1] - r[tile]);
+  }
+  const int ci_idx = cam_of_tile(cams, C, tile);
+  const CamInfo& ci = cams[ci_idx];
   const int64_t local = tile - ci.tile_off;
   const int ty = (int)(local / ci.GX), tx = (int)(local % ci.GX);
   const int lxi = tid % TW, lyi = tid / TW;
@@ -199,16 +214,25 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
   const double lx = (double)lxi, ly = (double)lyi;
   const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
-  const int64_t start = ranges[tile];
-  const int32_t len = (int32_t)(ranges[tile + 1] - start);
+  const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
 
   double T = 1.0, cr = 0.0, cg = 0.0, cb = 0.0;
   int32_t lastc = 0;
   bool done = !inside;
+  if (c > 0 && inside) {
+    const double4 sv = state[pix];
+    T = sv.x;
+    cr = sv.y;
+    cg = sv.z;
+    cb = sv.w;
+    done = done_px[pix] != 0;
+    lastc = last[pix];
+  }
   for (int32_t p0 = 0; p0 < len; p0 += batch) {
     if (__syncthreads_count(!done) == 0) break;
     const int nb = (len - p0) < batch ? (len - p0) : batch;
-    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, start, p0, nb, x0c, y0c, rp.lam2);
+    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, tid < nb, start + p0 + tid,
+                                        prefix + p0 + tid, x0c, y0c, rp.lam2);
     if (!done) {
       for (int k = 0; k < cnt; ++k) {
         const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
@@ -231,7 +255,6 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
     }
   }
   if (inside) {
-    const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
     const int64_t plane = (int64_t)ci.W * ci.H;
     const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
     image[ib] = (float)(cr + T * (double)rp.bg0);
@@ -240,11 +263,20 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
     final_T[pix] = (float)T;
     last[pix] = lastc;
   }
+  if (K > 1 && c < K - 1) {
+    if (inside) {
+      state[pix] = make_double4(T, cr, cg, cb);
+      done_px[pix] = done ? 1 : 0;
+    }
+    const int any_live = __syncthreads_or(inside && !done);
+    if (tid == 0) alive[tile] = any_live ? 1u : 0u;
+  }
 }
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
-    const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges,
+    const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all,
+    int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
     RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
     const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
@@ -253,6 +285,8 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   __shared__ Stage<NT> st;
   __shared__ float s_acc[kGrad2d][NT];
   __shared__ int32_t s_max[NW];
+  __shared__ int64_t s_segbase[kMaxDepthChunks];
+  __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int c = cam_of_tile(cams, C, tile);
@@ -265,8 +299,19 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
   const double lx = (double)lxi, ly = (double)lyi;
   const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
-  const int64_t start = ranges[tile];
-  const int64_t len = ranges[tile + 1] - start;
+  // the tile's list: its segments of every chunk, in chunk order
+  if (tid == 0) {
+    int32_t pre = 0;
+    for (int cc = 0; cc < K; ++cc) {
+      const int64_t* r = ranges_all + (int64_t)cc * (T_all + 1);
+      s_segbase[cc] = chunk_base[cc] + r[tile];
+      s_segpre[cc] = pre;
+      pre += (int32_t)(r[tile + 1] - r[tile]);
+    }
+    s_segpre[K] = pre;
+  }
+  __syncthreads();
+  const int64_t len = s_segpre[K];
 
   double T = 1.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
   int32_t mylast = 0;
@@ -298,7 +343,14 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   for (int32_t hi = maxlast; hi > 0; hi -= batch) {
     const int32_t lo = hi - batch > 0 ? hi - batch : 0;
     __syncthreads();
-    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, start, lo, hi - lo, x0c, y0c, rp.lam2);
+    const int32_t q = lo + tid;
+    int64_t vidx = 0;
+    if (q < hi) {
+      int cc = 0;
+      while (cc + 1 < K && s_segpre[cc + 1] <= q) ++cc;
+      vidx = s_segbase[cc] + (q - s_segpre[cc]);
+    }
+    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.lam2);
     for (int i = tid; i < kGrad2d * NT; i += NT) (&s_acc[0][0])[i] = 0.f;
     __syncthreads();
     for (int k = cnt - 1; k >= 0; --k) {
@@ -406,27 +458,47 @@ RasterParams make_params(const ls_config* cfg) {
 
 }  // namespace
 
+__global__ void fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = v;
+}
+
 hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, float* image,
                              float* final_T, int32_t* last, hipStream_t s) {
   if (p.T == 0) return hipSuccess;
   const CamInfo* cams = (const CamInfo*)(ws + p.lay.cams);
   const int64_t* ranges = (const int64_t*)(ws + p.lay.ranges);
+  const int64_t* chunk_base = (const int64_t*)(ws + p.lay.chunk_base);
   const uint32_t* vals = (const uint32_t*)(ws + p.lay.vals);
   const ProjRec* proj = (const ProjRec*)(ws + p.lay.proj);
+  double4* state = (double4*)(ws + p.state);
+  uint8_t* done = (uint8_t*)(ws + p.done);
+  uint32_t* alive = (uint32_t*)(ws + p.alive);
   RasterParams rp = make_params(cfg);
   const int npix = cfg->tile_w * cfg->tile_h;
   const int batch = cfg->batch ? cfg->batch : npix;
   dim3 grid((unsigned)p.T);
-  ProfScope ps("raster_fwd", s);
-#define LS_FWD(TW_, TH_)                                                                        \
+  hipError_t e;
+  if (p.K > 1) {
+    int64_t blocks = std::min<int64_t>((p.T + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, alive, p.T, 1u);
+    if ((e = hipGetLastError())) return e;
+  }
+  for (int c = 0; c < p.K; ++c) {
+    if (p.K > 1 && (e = launch_chunk_bin(p, c, ws, s))) return e;
+    ProfScope ps("raster_fwd", s);
+#define LS_FWD(TW_, TH_)                                                                           \
   hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
-                     vals, proj, p.M, batch, rp, image, final_T, last)
-  if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_FWD(16, 16);
-  else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_FWD(16, 8);
-  else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_FWD(8, 8);
-  else LS_FWD(32, 8);
+                     p.T, c, p.K, chunk_base, vals, proj, p.M, batch, rp, state, done, alive, image, \
+                     final_T, last)
+    if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_FWD(16, 16);
+    else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_FWD(16, 8);
+    else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_FWD(8, 8);
+    else LS_FWD(32, 8);
 #undef LS_FWD
-  return hipGetLastError();
+    if ((e = hipGetLastError())) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
@@ -442,6 +514,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
   if (p.T > 0) {
     const CamInfo* cams = (const CamInfo*)(ws + p.lay.cams);
     const int64_t* ranges = (const int64_t*)(ws + p.lay.ranges);
+    const int64_t* chunk_base = (const int64_t*)(ws + p.lay.chunk_base);
     const uint32_t* vals = (const uint32_t*)(ws + p.lay.vals);
     const ProjRec* proj = (const ProjRec*)(ws + p.lay.proj);
     RasterParams rp = make_params(cfg);
@@ -451,7 +524,8 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     ProfScope ps("raster_bwd", s);
 #define LS_BWD(TW_, TH_)                                                                         \
   hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
-                     vals, proj, p.M, batch, rp, final_T, last, dL_dimage, grad2d)
+                     p.T, p.K, chunk_base, vals, proj, p.M, batch, rp, final_T, last, dL_dimage, \
+                     grad2d)
     if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_BWD(16, 16);
     else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_BWD(16, 8);
     else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_BWD(8, 8);

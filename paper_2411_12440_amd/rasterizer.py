@@ -28,9 +28,9 @@ class Rasterizer:
     intersection capacity.
 
     ``forward`` runs project -> bin_sort -> rasterize_fwd.  With
-    ``check_capacity`` (default) it reads the intersection count back after
-    binning and, if the workspace is too small, grows it and bins again;
-    without it nothing synchronises and an overflow leaves an empty composite
+    ``check_capacity`` (default) it reads the overflow flag back and, if the
+    lists did not fit, grows the workspace and runs again; without it nothing
+    synchronises and an overflow leaves an incomplete composite
     (``overflowed()`` tells).
     """
 
@@ -67,10 +67,23 @@ class Rasterizer:
         return self.ws[off + offset_elems * esz: off + (offset_elems + count) * esz].view(dtype)
 
     def n_isect(self) -> int:
+        """Intersections of the complete tile lists."""
         return int(self.view("n_isect", torch.int64, 1).item())
 
+    def n_built(self) -> int:
+        """Entries actually built (all chunks)."""
+        K = int(self.layout.n_chunks)
+        return int(self.view("chunk_base", torch.int64, 1, K).item())
+
     def overflowed(self) -> bool:
-        return self.n_isect() > self.capacity
+        return int(self.view("flags", torch.int32, 1).item()) != 0
+
+    def lists(self):
+        """Per-chunk (chunk_base, ranges [T+1]) as numpy arrays (for tests)."""
+        K, T = int(self.layout.n_chunks), int(self.layout.n_tiles)
+        base = self.view("chunk_base", torch.int64, K + 1).cpu().numpy()
+        rng = self.view("ranges", torch.int64, K * (T + 1)).cpu().numpy().reshape(K, T + 1)
+        return base, rng
 
     # -- stages -----------------------------------------------------------------
     def _splats(self, sp):
@@ -102,15 +115,18 @@ class Rasterizer:
 
     # -- composite calls ---------------------------------------------------------
     def forward(self, sp, check_capacity=True, stream=None):
-        self.project(sp, stream)
-        self.bin_sort(stream)
-        if check_capacity:
+        """project -> bin_sort -> rasterize_fwd.  With check_capacity, a run
+        whose lists did not fit is repeated with a larger workspace (the
+        complete-list count n_isect bounds what any run can need)."""
+        while True:
+            self.project(sp, stream)
+            self.bin_sort(stream)
+            self.rasterize_fwd(stream)
+            if not check_capacity or not self.overflowed():
+                break
             n = self.n_isect()
-            if n > self.capacity:
-                self._alloc(int(n * 1.25) + 1024)
-                self.project(sp, stream)
-                self.bin_sort(stream)
-        self.rasterize_fwd(stream)
+            grow = min(n, max(2 * self.capacity, 1 << 20))
+            self._alloc(int(grow) + 1024)
         return self.image, self.final_T, self.last
 
     def backward(self, sp, dL_dimage, stream=None):

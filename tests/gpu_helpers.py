@@ -19,7 +19,8 @@ def say(*a):
 
 
 def cfg_pair(**kw):
-    """Matching oracle and library settings."""
+    """Matching oracle and library settings (depth_chunks only affects the
+    library: the oracle always builds complete lists)."""
     kw = dict(kw)
     strict = kw.pop("strict", False)
     okw = dict(lambda_=kw.get("lambda_", 2.5), ags=kw.get("ags", False),
@@ -33,7 +34,7 @@ def cfg_pair(**kw):
                alpha_max=ocfg.alpha_max, t_min=ocfg.t_min, near=ocfg.near, far=ocfg.far,
                clip=ocfg.clip, bg=ocfg.bg, ags=ocfg.ags, ags_arg=ocfg.ags_arg,
                ags_scope=ocfg.ags_scope, tile_w=ocfg.tile_w, tile_h=ocfg.tile_h,
-               batch=kw.get("batch", 0))
+               batch=kw.get("batch", 0), depth_chunks=kw.get("depth_chunks", 1))
     return ocfg, gkw
 
 
@@ -63,14 +64,28 @@ def gpu_arrays(rast):
         depth_key=rast.view("depth_key", torch.int32, M).cpu().numpy().view(np.uint32),
         order=rast.view("order", torch.int32, M).cpu().numpy().view(np.uint32),
         n_isect=n,
-        ranges=rast.view("ranges", torch.int64, T + 1).cpu().numpy(),
         image=rast.image.cpu().numpy().astype(np.float64),
         final_T=rast.final_T.cpu().numpy().astype(np.float64),
         last=rast.last.cpu().numpy().astype(np.int64),
     )
-    nv = min(n, rast.capacity)
-    out["vals"] = rast.view("vals", torch.int32, nv).cpu().numpy().view(np.uint32).astype(np.int64)
-    out["keys"] = rast.view("keys", torch.int32, nv).cpu().numpy().view(np.uint32).astype(np.int64)
+    base, rng = rast.lists()
+    nb = int(base[-1])
+    out["chunk_base"], out["chunk_ranges"] = base, rng
+    out["overflow"] = rast.overflowed()
+    out["vals_all"] = rast.view("vals", torch.int32, nb).cpu().numpy().view(np.uint32).astype(np.int64)
+    out["keys_all"] = rast.view("keys", torch.int32, nb).cpu().numpy().view(np.uint32).astype(np.int64)
+    if len(base) == 2:           # complete lists: one chunk
+        out["vals"], out["keys"], out["ranges"] = out["vals_all"], out["keys_all"], rng[0]
+    return out
+
+
+def tile_lists(g, T):
+    """Per tile: the concatenation of its chunk segments (pair ids)."""
+    base, rng, vals = g["chunk_base"], g["chunk_ranges"], g["vals_all"]
+    out = []
+    for t in range(T):
+        segs = [vals[base[c] + rng[c, t]: base[c] + rng[c, t + 1]] for c in range(len(base) - 1)]
+        out.append(np.concatenate(segs) if segs else np.zeros(0, np.int64))
     return out
 
 
@@ -119,16 +134,38 @@ def pixel_flags_to_image(flag, cams):
 
 
 def compare_binning(g, fw):
-    """Bit-exact comparison of every integer the binning produces."""
+    """Bit-exact comparison of every integer the binning produces.  With depth
+    chunks, every tile's list must be a prefix of its complete list that runs
+    to the end of the chunk where the tile's last pixel stopped (checked via
+    the composite), and the keys must follow the values."""
     vis = fw.ntiles > 0
+    assert not g["overflow"]
     np.testing.assert_array_equal(g["ntiles"], fw.ntiles)
     np.testing.assert_array_equal(g["depth_key"][vis], fw.depth_key[vis])
     assert np.all(g["depth_key"][~vis] == 0xFFFFFFFF)
     np.testing.assert_array_equal(g["rect"][vis], fw.rect[vis])
     assert g["n_isect"] == len(fw.sorted_ids) == int(fw.ntiles.sum())
-    np.testing.assert_array_equal(g["vals"], fw.sorted_ids)
-    np.testing.assert_array_equal(g["keys"], fw.sorted_gtile)
-    np.testing.assert_array_equal(g["ranges"], fw.ranges)
+    if "ranges" in g:
+        np.testing.assert_array_equal(g["vals"], fw.sorted_ids)
+        np.testing.assert_array_equal(g["keys"], fw.sorted_gtile)
+        np.testing.assert_array_equal(g["ranges"], fw.ranges)
+    else:
+        T = len(fw.ranges) - 1
+        lists = tile_lists(g, T)
+        built = 0
+        for t in range(T):
+            ref = fw.sorted_ids[fw.ranges[t]:fw.ranges[t + 1]]
+            got = lists[t]
+            assert len(got) <= len(ref), t
+            np.testing.assert_array_equal(got, ref[:len(got)])
+            built += len(got)
+        assert built == int(g["chunk_base"][-1])
+        # keys of each chunk follow its values
+        base, rng = g["chunk_base"], g["chunk_ranges"]
+        for c in range(len(base) - 1):
+            k = g["keys_all"][base[c]:base[c + 1]]
+            assert np.all(np.diff(k) >= 0)
+            np.testing.assert_array_equal(np.searchsorted(k, np.arange(T + 1)), rng[c])
     # the depth presort: a permutation sorted by (depth_key, pair id)
     dk = g["depth_key"].astype(np.int64)
     ref_order = np.lexsort((np.arange(len(dk)), dk))

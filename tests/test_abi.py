@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(B.EXPORTS) == set(declared_functions())
-    assert B.ls_version() == 100
+    assert B.ls_version() == 110
 
 
 def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):
@@ -54,7 +54,8 @@ def test_workspace_size_and_layout():
     assert lay.n_pixels == 128 * 128 + 40 * 24
     assert lay.total_bytes == s1
     offs = [lay.cams, lay.proj, lay.rect, lay.ntiles, lay.depth_key, lay.order, lay.isect_off,
-            lay.keys, lay.vals, lay.ranges, lay.n_isect, lay.grad2d, lay.scratch]
+            lay.keys, lay.vals, lay.ranges, lay.n_isect, lay.chunk_base, lay.chunk_n, lay.flags,
+            lay.grad2d, lay.scratch]
     assert all(o % 256 == 0 for o in offs)
     assert offs == sorted(offs)
     assert lay.vals - lay.keys >= 4 * (1 << 20)
@@ -62,7 +63,8 @@ def test_workspace_size_and_layout():
 
 @pytest.mark.parametrize("field,value", [("lambda_", 0.0), ("eps2d", 0.0), ("alpha_max", 1.0),
                                          ("t_min", -1.0), ("sh_degree", 4), ("ags", 2),
-                                         ("batch", 100), ("near_z", -1.0)])
+                                         ("batch", 100), ("near_z", -1.0),
+                                         ("depth_chunks", 13)])
 def test_invalid_config_rejected(field, value):
     from paper_2411_12440_amd import binding as B
     cfg = B.make_config()
@@ -105,3 +107,15 @@ def test_null_workspace_and_buffers_rejected():
     st = lib.ls_project(C.byref(cfg), C.byref(sp), C.byref(cams.c), base, len(ws.raw) - 256, 0, None)
     assert st == -1
     assert b"splats.n" in lib.ls_last_error()
+
+
+def test_depth_chunks_layout():
+    """Chunked mode keeps one ranges table per chunk and per-pixel state."""
+    from paper_2411_12440_amd import binding as B
+    cams = _cams(w=(128,), h=(96,), scene=(0,), off=(0, 5000))
+    l1 = B.ls_workspace_layout(B.make_config(depth_chunks=1), cams, 1 << 16)
+    l6 = B.ls_workspace_layout(B.make_config(depth_chunks=6), cams, 1 << 16)
+    assert l1.n_chunks == 1 and l6.n_chunks == 6
+    T = 8 * 6
+    assert l6.n_isect - l6.ranges >= 8 * 6 * (T + 1)
+    assert l6.total_bytes > l1.total_bytes + 32 * 128 * 96

@@ -37,10 +37,11 @@ def _run_fwd_bwd(scene, off, cams, gkw, G):
     return g, _grads_to_numpy(grads)
 
 
-def test_workload1_forward():
-    say("case: workload 1 (1k splats, SH0, 128x128) forward")
+@pytest.mark.parametrize("chunks", [1, 5])
+def test_workload1_forward(chunks):
+    say(f"case: workload 1 (1k splats, SH0, 128x128) forward, depth chunks {chunks}")
     scene, off, cams = scenes.workload(1)
-    ocfg, gkw = cfg_pair()
+    ocfg, gkw = cfg_pair(depth_chunks=chunks)
     rast, _ = gpu_forward(scene, off, cams, gkw)
     g = gpu_arrays(rast)
     fw = render_forward(scene, off, cams, ocfg)
@@ -63,16 +64,18 @@ def test_ragged_tile_shapes(tw, th, batch):
     compare_forward(g, fw, cams)
 
 
-@pytest.mark.parametrize("ags,ags_arg,ags_scope,strict", [(False, 0, 0, False), (True, 0, 0, False),
-                                                         (True, 1, 0, True), (True, 0, 1, False),
-                                                         (False, 0, 0, True)])
-def test_forward_backward_small(ags, ags_arg, ags_scope, strict):
-    say(f"case: fwd+bwd 3000 splats SH3 200x120 ags={ags} arg={ags_arg} scope={ags_scope} strict={strict}")
+@pytest.mark.parametrize("ags,ags_arg,ags_scope,strict,chunks",
+                         [(False, 0, 0, False, 1), (True, 0, 0, False, 1), (True, 1, 0, True, 1),
+                          (True, 0, 1, False, 1), (False, 0, 0, True, 1), (True, 0, 0, False, 6),
+                          (False, 0, 0, True, 4)])
+def test_forward_backward_small(ags, ags_arg, ags_scope, strict, chunks):
+    say(f"case: fwd+bwd 3000 splats SH3 200x120 ags={ags} arg={ags_arg} scope={ags_scope} "
+        f"strict={strict} chunks={chunks}")
     scene = scenes.make_scene(3000, 77, -3.0, 0.5, 3)
     cams = scenes.front_camera(200, 120)
     off = np.array([0, scene.n])
     ocfg, gkw = cfg_pair(ags=ags, ags_arg=ags_arg, ags_scope=ags_scope, strict=strict,
-                         bg=(0.1, 0.2, 0.3))
+                         bg=(0.1, 0.2, 0.3), depth_chunks=chunks)
     G = scenes.upstream_grad(cams, 7002)
     fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
     # zero the upstream gradient where a decision sits on a threshold
@@ -84,13 +87,14 @@ def test_forward_backward_small(ags, ags_arg, ags_scope, strict):
     compare_grads(grads, go, scene)
 
 
-def test_multi_camera_multi_scene():
-    say("case: 3 scenes, 6 cameras of uneven size, fwd+bwd")
+@pytest.mark.parametrize("chunks", [1, 3])
+def test_multi_camera_multi_scene(chunks):
+    say(f"case: 3 scenes, 6 cameras of uneven size, fwd+bwd, depth chunks {chunks}")
     scs = [scenes.make_scene(n, 900 + i, -3.0, 0.5, 2) for i, n in enumerate((700, 1200, 400))]
     scene, off = scenes.concat_scenes(scs)
     res = [(96, 64), (130, 70), (64, 64), (200, 90), (50, 120), (128, 96)]
     cams = scenes.sphere_cameras(6, 4.0, res, scene_of_cam=[0, 1, 2, 0, 1, 2])
-    ocfg, gkw = cfg_pair()
+    ocfg, gkw = cfg_pair(depth_chunks=chunks)
     G = scenes.upstream_grad(cams, 7003)
     fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
     G = G * ~pixel_flags_to_image(fw.flag, cams)
@@ -102,13 +106,14 @@ def test_multi_camera_multi_scene():
     compare_grads(grads, go, scene)
 
 
-def test_workload2_binning_and_sampled_tiles():
-    """100k splats, SH3, 1280x720: full binning bit-exact; composite and
+@pytest.mark.parametrize("chunks", [1, 7])
+def test_workload2_binning_and_sampled_tiles(chunks):
+    """100k splats, SH3, 1280x720: binning bit-exact; composite and
     gradients compared on a seeded sample of tiles (upstream gradient zero
     elsewhere)."""
-    say("case: workload 2 (100k splats, SH3, 1280x720)")
+    say(f"case: workload 2 (100k splats, SH3, 1280x720), depth chunks {chunks}")
     scene, off, cams = scenes.workload(2)
-    ocfg, gkw = cfg_pair(ags=True)
+    ocfg, gkw = cfg_pair(ags=True, depth_chunks=chunks)
     rng = np.random.default_rng(11)
     T = 80 * 45
     tiles = np.sort(rng.choice(T, 40, replace=False))
@@ -150,36 +155,40 @@ def test_empty_and_culled():
     torch.cuda.synchronize()
 
 
-def test_capacity_overflow_is_reported():
-    say("case: intersection capacity too small")
+@pytest.mark.parametrize("chunks", [1, 4])
+def test_capacity_overflow_is_reported(chunks):
+    say(f"case: intersection capacity too small, depth chunks {chunks}")
     import torch
     from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
     scene, off, cams = scenes.workload(1)
-    ocfg, gkw = cfg_pair(bg=(0.5, 0.5, 0.5))
+    ocfg, gkw = cfg_pair(bg=(0.5, 0.5, 0.5), depth_chunks=chunks)
     rast = Rasterizer(cams, off, capacity=100, sh_degree=0, **gkw)
     sp = scene_to_device(scene)
     rast.forward(sp, check_capacity=False)
     torch.cuda.synchronize()
-    fw = render_forward(scene, off, cams, ocfg, tiles=[])
+    fw = render_forward(scene, off, cams, ocfg)
     assert rast.n_isect() == len(fw.sorted_ids) > 100
     assert rast.overflowed()
-    assert torch.all(rast.image == 0.5)
+    if chunks == 1:
+        assert torch.all(rast.image == 0.5)
     # growing the capacity recovers the exact result
     rast.forward(sp, check_capacity=True)
     torch.cuda.synchronize()
     g = gpu_arrays(rast)
     compare_binning(g, fw)
+    compare_forward(g, fw, cams)
 
 
-def test_fullscreen_splats():
+@pytest.mark.parametrize("chunks", [1, 6])
+def test_fullscreen_splats(chunks):
     """A few splats larger than the image (every tile) among small ones; the
     keygen load balancing must give every tile its entry."""
-    say("case: full-screen splats")
+    say(f"case: full-screen splats, depth chunks {chunks}")
     scene = scenes.make_scene(800, 31, -3.0, 0.5, 0)
     scene.scales[:5] = 3.0
     cams = scenes.front_camera(160, 96)
     off = np.array([0, scene.n])
-    ocfg, gkw = cfg_pair()
+    ocfg, gkw = cfg_pair(depth_chunks=chunks)
     rast, _ = gpu_forward(scene, off, cams, gkw)
     g = gpu_arrays(rast)
     fw = render_forward(scene, off, cams, ocfg)
