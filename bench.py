@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--views", type=int, default=8)
     ap.add_argument("--splats", type=int, default=3_200_000)
     ap.add_argument("--ags", type=int, default=1)
+    ap.add_argument("--depth-chunks", type=int, default=7)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -67,7 +68,7 @@ def make_workload(n_splats, views):
 
 def kernel_cost(name, w):
     """(bound, amount per launch, unit) for the kernels we can price."""
-    N, M, n, K, Q = w["N"], w["M"], w["n_isect"], w["K"], w["Q"]
+    N, M, n, K, Q = w["N"], w["M"], w["n_built"], w["K"], w["Q"]
     splat_bytes = 44 + 12 * K
     if name == "tilesort_downsweep":
         return "hbm", 16.0 * n, "B"
@@ -77,7 +78,7 @@ def kernel_cost(name, w):
         return "hbm", 16.0 * M, "B"
     if name == "presort_upsweep":
         return "hbm", 4.0 * M, "B"
-    if name == "keygen":
+    if name in ("keygen", "keygen_write"):
         return "hbm", 8.0 * n + 20.0 * M, "B"
     if name == "project":
         return "hbm", float(splat_bytes) * N + 80.0 * M, "B"
@@ -192,7 +193,7 @@ def main():
     scene, cams = make_workload(args.splats, args.views)
     sp = scene_to_device(scene, dev)
     G_all = torch.from_numpy(S.upstream_grad(cams, 7004)).to(dev)
-    cfgkw = dict(sh_degree=3, ags=bool(args.ags))
+    cfgkw = dict(sh_degree=3, ags=bool(args.ags), depth_chunks=args.depth_chunks)
     off = np.array([0, scene.n])
     P = int(sum(int(w) * int(h) for w, h in zip(cams.width, cams.height)))
 
@@ -202,8 +203,8 @@ def main():
     rast.forward(sp, check_capacity=True)
     torch.cuda.synchronize()
     n_isect = rast.n_isect()
-    if n_isect * 1.02 > rast.capacity:
-        rast._alloc(int(n_isect * 1.05) + 4096)
+    n_built = rast.n_built()
+    rast._alloc(max(int(n_built * 1.05) + 4096, n_isect // 12))
     grads = {k: torch.empty_like(v) for k, v in sp.items()}
 
     def step_batched():
@@ -244,7 +245,7 @@ def main():
             r = Rasterizer(one, off, device=dev, capacity=1 << 24, **cfgkw)
             r.forward(sp, check_capacity=True)
             torch.cuda.synchronize()
-            r._alloc(int(r.n_isect() * 1.05) + 4096)
+            r._alloc(max(int(r.n_built() * 1.05) + 4096, r.n_isect() // 12))
             npx = int(cams.width[c]) * int(cams.height[c])
             g_v = G_all[3 * pix_off: 3 * (pix_off + npx)]
             pix_off += npx
@@ -254,9 +255,10 @@ def main():
             for r, g_v, gr in views:
                 r.project(sp)
                 r.bin_sort()
-                if r.n_isect() > r.capacity:        # host read-back, as a per-view loop does
-                    raise RuntimeError("per-view capacity overflow")
+                r.n_isect()                         # host read-back, as a per-view loop does
                 r.rasterize_fwd()
+                if r.overflowed():
+                    raise RuntimeError("per-view capacity overflow")
                 r.rasterize_bwd(sp, g_v, gr)
 
         for _ in range(args.warmup):
@@ -275,7 +277,7 @@ def main():
         del views
 
     # ---- roofline of the dominant kernel --------------------------------------
-    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, K=16, Q=Q)
+    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q)
     kernels = []
     for name, launches, total in ktimes:
         kernels.append(dict(kernel=name, launches=launches, avg_ms=round(total / launches, 4),
@@ -321,6 +323,7 @@ def main():
         "config": {"workload": "3.2M splats SH3, log-scale N(-4,1), 8 views 1920x1080 on a "
                                "radius-4 sphere, fwd+bwd, batched",
                    "views": cams.n, "pixels_per_step": P, "n_isect": n_isect,
+                   "entries_built": n_built, "depth_chunks": args.depth_chunks,
                    "pairs_to_last": Q, "ags": bool(args.ags), "tile": "16x16",
                    "parallelism": "single GPU"},
         "per_view": per_view,

@@ -151,7 +151,13 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   int64_t sb = (p->M + 1 + kScanThreads * 16 - 1) / (kScanThreads * 16);
   p->scan_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(sb, kMaxScanBlocks));
   p->scan_part = take(8 * (size_t)(p->scan_blocks + 1));
-  p->n_spans = (std::max<int64_t>(cap, 1) + kKeygenSpan - 1) / kKeygenSpan + 1;
+  // The span table covers the complete lists; with depth chunks the capacity
+  // only holds the entries actually built, so the table is sized for
+  // kSpanCover times the capacity (2 bytes per covered intersection).
+  {
+    const int64_t cover = std::max<int64_t>(cap, 1) * (p->K > 1 ? kSpanCover : 1);
+    p->n_spans = (cover + kKeygenSpan - 1) / kKeygenSpan + 2;
+  }
   p->span_owner = take(4 * (size_t)p->n_spans);
   p->span_cnt = take(4 * (size_t)p->n_spans);
   p->span_off = take(4 * (size_t)p->n_spans);

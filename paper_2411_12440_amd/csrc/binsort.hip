@@ -387,18 +387,23 @@ __global__ __launch_bounds__(kScanThreads) void scan_down(In in, Out out, const 
 
 // After the pair scan: total intersections, and (complete-list mode) the
 // single chunk's count clamped to the capacity.
+// The span table must cover every span of the complete lists (plus the
+// terminal entry); otherwise the run is flagged as an overflow and no list is
+// built.
 __global__ void pairs_finalize(const int64_t* __restrict__ total, int64_t M,
                                int64_t* __restrict__ isect_off, int64_t* __restrict__ n_isect,
                                int64_t* __restrict__ chunk_base, int64_t* __restrict__ chunk_n,
-                               int32_t* __restrict__ flags, int64_t cap, int full_lists) {
+                               int32_t* __restrict__ flags, int64_t cap, int64_t n_spans,
+                               int full_lists) {
   if (threadIdx.x != 0) return;
   const int64_t n = *total;
   isect_off[M] = n;
   *n_isect = n;
   chunk_base[0] = 0;
-  flags[0] = 0;
+  const bool covered = (n + kKeygenSpan - 1) / kKeygenSpan + 1 < n_spans;
+  flags[0] = covered ? 0 : 1;
   if (full_lists) {
-    const bool ok = n <= cap;
+    const bool ok = covered && n <= cap;
     chunk_n[0] = ok ? n : 0;
     chunk_base[1] = ok ? n : 0;
     if (!ok) flags[0] = 1;
@@ -545,9 +550,13 @@ __global__ __launch_bounds__(kKeygenThreads) void keygen_chunk_kernel(
     const uint32_t* __restrict__ alive, uint32_t* __restrict__ span_cnt,
     int64_t* __restrict__ n_spans_out, const uint32_t* __restrict__ span_off,
     const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
-    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int32_t* __restrict__ flags, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ SpanTables t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (flags[0] != 0) {               // overflow: the span table may not cover the lists
+    if (kCount && blockIdx.x == 0 && tid == 0) *n_spans_out = 0;
+    return;
+  }
   const int64_t E0 = isect_off[pos_lo], E1 = isect_off[pos_hi];
   const int64_t s0 = E0 / kKeygenSpan;
   const int64_t s1 = (E1 > E0) ? (E1 + kKeygenSpan - 1) / kKeygenSpan : s0;
@@ -752,7 +761,7 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
     hipLaunchKernelGGL((scan_down<PairCount, PairOffsets>), dim3(B), dim3(kScanThreads), 0, s, in,
                        out, nullptr, M, B, part);
     hipLaunchKernelGGL(pairs_finalize, dim3(1), dim3(64), 0, s, part + B, M, isect_off, n_isect,
-                       chunk_base, chunk_n, flags, p.cap, p.K == 1 ? 1 : 0);
+                       chunk_base, chunk_n, flags, p.cap, p.n_spans, p.K == 1 ? 1 : 0);
     if ((e = hipGetLastError())) return e;
   }
   if (p.K > 1) return hipSuccess;   // lists are built chunk by chunk by the rasterizer
@@ -797,7 +806,7 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
                          order, isect_off, (const ushort4*)(ws + p.lay.rect),
                          (const CamInfo*)(ws + p.lay.cams), p.C, M, lo, hi,
                          (const uint32_t*)(ws + p.span_owner), alive, span_cnt, n_spans, nullptr,
-                         nullptr, nullptr, nullptr, nullptr);
+                         nullptr, nullptr, flags, nullptr, nullptr);
     }
     {
       int64_t* part = (int64_t*)(ws + p.scan_part);
@@ -819,7 +828,7 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
                          order, isect_off, (const ushort4*)(ws + p.lay.rect),
                          (const CamInfo*)(ws + p.lay.cams), p.C, M, lo, hi,
                          (const uint32_t*)(ws + p.span_owner), alive, nullptr, nullptr, span_off,
-                         chunk_base, chunk_n, k0, v0);
+                         chunk_base, chunk_n, flags, k0, v0);
     }
     if ((e = hipGetLastError())) return e;
   } else {

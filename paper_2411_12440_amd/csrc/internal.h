@@ -78,6 +78,7 @@ constexpr int kMaxSortBlocks = 1024;
 constexpr int kScanThreads = 256;
 constexpr int kKeygenSpan = 2048;   // output entries per key-generation block iteration
 constexpr int kMaxDepthChunks = 12;
+constexpr int kSpanCover = 16;   // span-table coverage per unit of capacity (chunk mode)
 constexpr int kMaxScanBlocks = 1024;
 
 // ---------------------------------------------------------------------------
