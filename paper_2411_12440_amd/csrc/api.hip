@@ -154,15 +154,17 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   // The span table covers the complete lists; with depth chunks the capacity
   // only holds the entries actually built, so the table is sized for
   // kSpanCover times the capacity (2 bytes per covered intersection).
-  {
-    const int64_t cover = std::max<int64_t>(cap, 1) * (p->K > 1 ? kSpanCover : 1);
-    p->n_spans = (cover + kKeygenSpan - 1) / kKeygenSpan + 2;
-  }
+  // complete lists: owner pair of every key-generation span
+  p->n_spans = p->K == 1 ? (std::max<int64_t>(cap, 1) + kKeygenSpan - 1) / kKeygenSpan + 2 : 1;
   p->span_owner = take(4 * (size_t)p->n_spans);
-  p->span_cnt = take(4 * (size_t)p->n_spans);
-  p->span_off = take(4 * (size_t)p->n_spans);
+  // depth chunks: per-pair alive counts and offsets, tile summed-area table
+  p->span_cnt = take(4 * (p->K > 1 ? M : 1));
+  p->span_off = take(4 * (p->K > 1 ? M : 1));
   p->chunk_spans = take(8 * K);
   p->alive = take(4 * T);
+  p->sat = take(4 * T);
+  p->dcnt = take(4 * M);
+  p->drect = take(8 * M);
   if (p->K > 1) {
     p->state = take(32 * (size_t)p->P);
     p->done = take((size_t)p->P);

@@ -26,9 +26,10 @@
 // chunk only emits entries for tiles that still have a pixel whose
 // transmittance has not run out.  Each tile's list is then the concatenation
 // of its chunk segments: a prefix of the complete list that holds every entry
-// the composite can reach.  Entries of a chunk are compacted in order
-// (count, scan, write), so the chunk's list is still exactly in (tile, depth,
-// pair id) order.
+// the composite can reach.  A per-camera summed-area table of the alive
+// tiles lets each pair count its alive tiles in O(1) (count, scan, write),
+// so the chunk's entries keep exactly the (tile, depth, pair id) order and
+// pairs whose rectangle holds no alive tile cost four loads.
 //
 // Radix passes: 8-bit digits, reduce-then-scan with a fixed grid of G blocks
 // (each owning a contiguous span, so the order is stable), 256 threads per
@@ -149,7 +150,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, const int64_t* base_dev,
     const int64_t* n_dev, int64_t n_host, int shift, int G, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ tot) {
+    const uint32_t* __restrict__ tot, const uint32_t* __restrict__ gcnt_src,
+    uint32_t* __restrict__ gcnt_dst, const ushort4* __restrict__ grect_src,
+    ushort4* __restrict__ grect_dst) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_wcnt[4][256];
   __shared__ uint32_t s_tstart[256];
@@ -233,8 +236,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
         const uint32_t d = (key >> shift) & 255u;
         const uint32_t gpos = s_base[d] + (uint32_t)p - s_tstart[d];
         if ((int64_t)gpos < n) {
+          const uint32_t val = s_vals[p];
           if (kWriteKeys) keys_out[gpos] = key;
-          vals_out[gpos] = s_vals[p];
+          vals_out[gpos] = val;
+          if (gcnt_dst) {           // per-pair data in the new order
+            gcnt_dst[gpos] = gcnt_src[val];
+            grect_dst[gpos] = grect_src[val];
+          }
         }
       }
     }
@@ -248,13 +256,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
 // block rescans its span) over inputs given by an accessor.
 // ---------------------------------------------------------------------------
 struct PairCount {          // tiles touched by the pair at depth position p
-  const uint32_t* order;
-  const uint32_t* ntiles;
-  int64_t M;
-  __device__ int64_t operator()(int64_t p) const {
-    const uint32_t m = order[p];
-    return (m < (uint64_t)M) ? (int64_t)ntiles[m] : 0;
-  }
+  const uint32_t* dcnt;
+  __device__ int64_t operator()(int64_t p) const { return (int64_t)dcnt[p]; }
 };
 
 struct SpanCount {
@@ -400,7 +403,7 @@ __global__ void pairs_finalize(const int64_t* __restrict__ total, int64_t M,
   isect_off[M] = n;
   *n_isect = n;
   chunk_base[0] = 0;
-  const bool covered = (n + kKeygenSpan - 1) / kKeygenSpan + 1 < n_spans;
+  const bool covered = !full_lists || (n + kKeygenSpan - 1) / kKeygenSpan + 1 < n_spans;
   flags[0] = covered ? 0 : 1;
   if (full_lists) {
     const bool ok = covered && n <= cap;
@@ -539,68 +542,92 @@ __global__ __launch_bounds__(kKeygenThreads) void keygen_kernel(
   }
 }
 
-// Chunk c of the depth order: entries [E_c, E_c1) with E = isect_off[pos].
-// kCount: per-span count of entries whose tile is alive.
-// !kCount: write those entries, in order, at base + span_off[span].
-template <bool kCount>
-__global__ __launch_bounds__(kKeygenThreads) void keygen_chunk_kernel(
-    const uint32_t* __restrict__ order, const int64_t* __restrict__ isect_off,
-    const ushort4* __restrict__ rect, const CamInfo* __restrict__ cams, int C, int64_t M,
-    int64_t pos_lo, int64_t pos_hi, const uint32_t* __restrict__ span_owner,
-    const uint32_t* __restrict__ alive, uint32_t* __restrict__ span_cnt,
-    int64_t* __restrict__ n_spans_out, const uint32_t* __restrict__ span_off,
-    const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
-    const int32_t* __restrict__ flags, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ SpanTables t;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (flags[0] != 0) {               // overflow: the span table may not cover the lists
-    if (kCount && blockIdx.x == 0 && tid == 0) *n_spans_out = 0;
-    return;
-  }
-  const int64_t E0 = isect_off[pos_lo], E1 = isect_off[pos_hi];
-  const int64_t s0 = E0 / kKeygenSpan;
-  const int64_t s1 = (E1 > E0) ? (E1 + kKeygenSpan - 1) / kKeygenSpan : s0;
-  if (kCount && blockIdx.x == 0 && tid == 0) *n_spans_out = s1 - s0;
-  int64_t base = 0;
-  if (!kCount) {
-    if (*chunk_n == 0) return;    // empty chunk or capacity overflow
-    base = *chunk_base;
-  }
-  for (int64_t s = s0 + blockIdx.x; s < s1; s += gridDim.x) {
-    span_setup(t, s, order, isect_off, rect, cams, C, M, span_owner);
-    const int64_t k0 = s * kKeygenSpan;
+// Per-camera inclusive summed-area table of the alive flags (one block per
+// camera): sat[t] counts the alive tiles in the rectangle from the camera's
+// first tile to t.
+__global__ __launch_bounds__(256) void alive_sat_kernel(const CamInfo* __restrict__ cams,
+                                                        const uint32_t* __restrict__ alive,
+                                                        uint32_t* __restrict__ sat) {
+  const CamInfo& ci = cams[blockIdx.x];
+  const int GX = ci.GX, GY = ci.GY;
+  uint32_t* S = sat + ci.tile_off;
+  const uint32_t* A = alive + ci.tile_off;
+  for (int r = threadIdx.x; r < GY; r += blockDim.x) {
     uint32_t run = 0;
-    const uint32_t out0 = kCount ? 0u : span_off[s - s0];
-    for (int r = 0; r < kKeygenSpan; r += kKeygenThreads) {
-      const int64_t k = k0 + r + tid;
-      bool keep = false;
-      uint32_t g = 0, m = 0;
-      if (k >= E0 && k < E1) {
-        span_entry(t, k0, r + tid, &g, &m);
-        keep = alive[g] != 0u;
-      }
-      const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
-      if (lane == 0) t.wcnt[wave] = (int32_t)__popcll(bal);
-      __syncthreads();
-      uint32_t wbase = 0, tot = 0;
-#pragma unroll
-      for (int w = 0; w < kKeygenThreads / 64; ++w) {
-        const uint32_t c = (uint32_t)t.wcnt[w];
-        wbase += (w < wave) ? c : 0u;
-        tot += c;
-      }
-      if (!kCount && keep) {
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        const int64_t dst = base + out0 + run + wbase + rank;
-        keys[dst] = g;
-        vals[dst] = m;
-      }
-      run += tot;
-      __syncthreads();
+    for (int x = 0; x < GX; ++x) {
+      run += A[(int64_t)r * GX + x] ? 1u : 0u;
+      S[(int64_t)r * GX + x] = run;
     }
-    if (kCount && tid == 0) span_cnt[s - s0] = run;
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < GX; x += blockDim.x) {
+    uint32_t run = 0;
+    for (int r = 0; r < GY; ++r) {
+      run += S[(int64_t)r * GX + x];
+      S[(int64_t)r * GX + x] = run;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t sat_query(const uint32_t* S, int GX, int x0, int y0, int x1,
+                                              int y1) {
+  auto at = [&](int x, int y) -> uint32_t {
+    return (x < 0 || y < 0) ? 0u : S[(int64_t)y * GX + x];
+  };
+  return at(x1, y1) - at(x0 - 1, y1) - at(x1, y0 - 1) + at(x0 - 1, y0 - 1);
+}
+
+// Chunk c of the depth order (pair positions [lo, hi)): for each pair the
+// number of alive tiles in its rectangle.
+__global__ __launch_bounds__(256) void chunk_count_kernel(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ dcnt,
+    const ushort4* __restrict__ drect, const CamInfo* __restrict__ cams, int C, int64_t M,
+    int64_t lo, int64_t hi, const uint32_t* __restrict__ sat, const int32_t* __restrict__ flags,
+    uint32_t* __restrict__ pcnt) {
+  const int64_t p = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= hi) return;
+  uint32_t k = 0;
+  if (flags[0] == 0 && dcnt[p] != 0) {
+    uint32_t m = order[p];
+    if (m >= (uint64_t)M) m = 0;
+    const ushort4 r = drect[p];
+    const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
+    k = sat_query(sat + ci.tile_off, ci.GX, r.x, r.y, r.z, r.w);
+  }
+  pcnt[p - lo] = k;
+}
+
+// Write the chunk's entries: each pair its alive tiles, row-major, at the
+// scanned offset; pairs follow the depth order, so the chunk's entries are in
+// the same relative order as in the complete lists.
+__global__ __launch_bounds__(256) void chunk_write_kernel(
+    const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
+    const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
+    const uint32_t* __restrict__ sat, const uint32_t* __restrict__ alive,
+    const uint32_t* __restrict__ pcnt, const uint32_t* __restrict__ poff,
+    const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int64_t p = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= hi || *chunk_n == 0) return;
+  uint32_t k = pcnt[p - lo];
+  if (k == 0) return;
+  uint32_t m = order[p];
+  if (m >= (uint64_t)M) m = 0;
+  const ushort4 r = drect[p];
+  const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
+  const uint32_t* S = sat + ci.tile_off;
+  int64_t dst = *chunk_base + poff[p - lo];
+  for (int ty = r.y; ty <= r.w && k > 0; ++ty) {
+    if (sat_query(S, ci.GX, r.x, ty, r.z, ty) == 0u) continue;
+    const int64_t row = ci.tile_off + (int64_t)ty * ci.GX;
+    for (int tx = r.x; tx <= r.z; ++tx) {
+      if (alive[row + tx]) {
+        keys[dst] = (uint32_t)(row + tx);
+        vals[dst] = m;
+        ++dst;
+        --k;
+      }
+    }
   }
 }
 
@@ -650,7 +677,9 @@ template <bool kIdent, bool kWriteKeys>
 hipError_t radix_pass(const char* const names[3], const uint32_t* kin, const uint32_t* vin,
                       uint32_t* kout, uint32_t* vout, const int64_t* base_dev,
                       const int64_t* n_dev, int64_t n_host, int shift, int G, uint32_t* hist,
-                      uint32_t* tot, hipStream_t s) {
+                      uint32_t* tot, hipStream_t s, const uint32_t* gcnt_src = nullptr,
+                      uint32_t* gcnt_dst = nullptr, const ushort4* grect_src = nullptr,
+                      ushort4* grect_dst = nullptr) {
   {
     ProfScope ps(names[0], s);
     hipLaunchKernelGGL(radix_upsweep, dim3(G), dim3(kSortThreads), 0, s, kin, base_dev, n_dev,
@@ -663,7 +692,8 @@ hipError_t radix_pass(const char* const names[3], const uint32_t* kin, const uin
   {
     ProfScope ps(names[2], s);
     hipLaunchKernelGGL((radix_downsweep<kIdent, kWriteKeys>), dim3(G), dim3(kSortThreads), 0, s,
-                       kin, vin, kout, vout, base_dev, n_dev, n_host, shift, G, hist, tot);
+                       kin, vin, kout, vout, base_dev, n_dev, n_host, shift, G, hist, tot,
+                       gcnt_src, gcnt_dst, grect_src, grect_dst);
   }
   return hipGetLastError();
 }
@@ -745,15 +775,19 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
                                      tot, s)))
       return e;
     if ((e = radix_pass<false, false>(kPreNames, kB, vB, nullptr, order, nullptr, nullptr, M, 24,
-                                      G, hist, tot, s)))
+                                      G, hist, tot, s, ntiles, (uint32_t*)(ws + p.dcnt),
+                                      (const ushort4*)(ws + p.lay.rect),
+                                      (ushort4*)(ws + p.drect))))
       return e;
   }
   // 2. scan of tile counts in depth order (+ span owners)
   {
     int64_t* part = (int64_t*)(ws + p.scan_part);
     const int B = scan_blocks_for(M);
-    PairCount in{order, ntiles, M};
-    PairOffsets out{isect_off, (uint32_t*)(ws + p.span_owner), p.n_spans, part + B};
+    PairCount in{(const uint32_t*)(ws + p.dcnt)};
+    // span owners serve the complete-list key generation only
+    PairOffsets out{isect_off, (uint32_t*)(ws + p.span_owner), p.K == 1 ? p.n_spans : 0,
+                    part + B};
     ProfScope ps("scan", s);
     hipLaunchKernelGGL(scan_reduce<PairCount>, dim3(B), dim3(kScanThreads), 0, s, in, nullptr, M,
                        B, part);
@@ -788,47 +822,45 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
   const int64_t M = p.M;
   int64_t* chunk_base = (int64_t*)(ws + p.lay.chunk_base) + c;
   int64_t* chunk_n = (int64_t*)(ws + p.lay.chunk_n) + c;
-  if (M > 0 && p.cap > 0) {
-    const int64_t* isect_off = (const int64_t*)(ws + p.lay.isect_off);
+  const int64_t lo = p.chunk_pos[c], hi = p.chunk_pos[c + 1];
+  if (M > 0 && p.cap > 0 && hi > lo) {
+    const CamInfo* cams = (const CamInfo*)(ws + p.lay.cams);
     const uint32_t* order = (const uint32_t*)(ws + p.lay.order);
-    int32_t* flags = (int32_t*)(ws + p.lay.flags);
-    uint32_t* span_cnt = (uint32_t*)(ws + p.span_cnt);
-    uint32_t* span_off = (uint32_t*)(ws + p.span_off);
-    int64_t* n_spans = (int64_t*)(ws + p.chunk_spans) + c;
     const uint32_t* alive = (const uint32_t*)(ws + p.alive);
-    const int64_t lo = p.chunk_pos[c], hi = p.chunk_pos[c + 1];
-    const int blocks = (int)std::min<int64_t>(p.n_spans, kKeygenBlocks);
+    uint32_t* sat = (uint32_t*)(ws + p.sat);
+    int32_t* flags = (int32_t*)(ws + p.lay.flags);
+    uint32_t* pcnt = (uint32_t*)(ws + p.span_cnt);
+    uint32_t* poff = (uint32_t*)(ws + p.span_off);
+    const uint32_t* dcnt = (const uint32_t*)(ws + p.dcnt);
+    const ushort4* drect = (const ushort4*)(ws + p.drect);
     uint32_t *k0, *v0;
     keygen_targets(p, ws, &k0, &v0);
+    const int64_t n = hi - lo;
+    const unsigned grid = (unsigned)((n + 255) / 256);
     {
-      ProfScope ps("keygen_count", s);
-      hipLaunchKernelGGL(keygen_chunk_kernel<true>, dim3(blocks), dim3(kKeygenThreads), 0, s,
-                         order, isect_off, (const ushort4*)(ws + p.lay.rect),
-                         (const CamInfo*)(ws + p.lay.cams), p.C, M, lo, hi,
-                         (const uint32_t*)(ws + p.span_owner), alive, span_cnt, n_spans, nullptr,
-                         nullptr, nullptr, flags, nullptr, nullptr);
+      ProfScope ps("chunk_count", s);
+      hipLaunchKernelGGL(alive_sat_kernel, dim3(p.C), dim3(256), 0, s, cams, alive, sat);
+      hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(256), 0, s, order, dcnt, drect, cams,
+                         p.C, M, lo, hi, sat, flags, pcnt);
     }
     {
       int64_t* part = (int64_t*)(ws + p.scan_part);
-      const int B = scan_blocks_for(p.n_spans);
-      SpanCount in{span_cnt};
-      SpanOffsets out{span_off};
+      const int B = scan_blocks_for(n);
+      SpanCount in{pcnt};
+      SpanOffsets out{poff};
       ProfScope ps("chunk_scan", s);
-      hipLaunchKernelGGL(scan_reduce<SpanCount>, dim3(B), dim3(kScanThreads), 0, s, in, n_spans,
-                         0, B, part);
+      hipLaunchKernelGGL(scan_reduce<SpanCount>, dim3(B), dim3(kScanThreads), 0, s, in, nullptr, n,
+                         B, part);
       hipLaunchKernelGGL(scan_parts, dim3(1), dim3(1024), 0, s, part, B);
       hipLaunchKernelGGL((scan_down<SpanCount, SpanOffsets>), dim3(B), dim3(kScanThreads), 0, s,
-                         in, out, n_spans, 0, B, part);
+                         in, out, nullptr, n, B, part);
       hipLaunchKernelGGL(chunk_finalize, dim3(1), dim3(64), 0, s, part + B, chunk_base, chunk_n,
                          flags, p.cap);
     }
     {
-      ProfScope ps("keygen_write", s);
-      hipLaunchKernelGGL(keygen_chunk_kernel<false>, dim3(blocks), dim3(kKeygenThreads), 0, s,
-                         order, isect_off, (const ushort4*)(ws + p.lay.rect),
-                         (const CamInfo*)(ws + p.lay.cams), p.C, M, lo, hi,
-                         (const uint32_t*)(ws + p.span_owner), alive, nullptr, nullptr, span_off,
-                         chunk_base, chunk_n, flags, k0, v0);
+      ProfScope ps("chunk_write", s);
+      hipLaunchKernelGGL(chunk_write_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams, p.C,
+                         M, lo, hi, sat, alive, pcnt, poff, chunk_base, chunk_n, k0, v0);
     }
     if ((e = hipGetLastError())) return e;
   } else {

@@ -61,7 +61,7 @@ struct Plan {
   // scratch sub-allocations (byte offsets from the workspace base)
   size_t sort_keys_b = 0, sort_vals_b = 0, pre_keys_a = 0, pre_keys_b = 0, pre_vals_a = 0, pre_vals_b = 0,
          hist = 0, digit_tot = 0, scan_part = 0, span_owner = 0, span_cnt = 0, span_off = 0,
-         chunk_spans = 0, alive = 0, state = 0, done = 0;
+         chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, dcnt = 0, drect = 0;
   int64_t n_spans = 0;        // entries of span_owner: ceil(cap / kKeygenSpan) + 1
   int32_t K = 1;              // depth chunks
   std::vector<int64_t> chunk_pos;   // [K + 1] pair positions in depth order
@@ -78,7 +78,6 @@ constexpr int kMaxSortBlocks = 1024;
 constexpr int kScanThreads = 256;
 constexpr int kKeygenSpan = 2048;   // output entries per key-generation block iteration
 constexpr int kMaxDepthChunks = 12;
-constexpr int kSpanCover = 16;   // span-table coverage per unit of capacity (chunk mode)
 constexpr int kMaxScanBlocks = 1024;
 
 // ---------------------------------------------------------------------------
