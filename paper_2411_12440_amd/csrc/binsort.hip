@@ -599,7 +599,12 @@ __global__ __launch_bounds__(256) void chunk_count_kernel(
 
 // Write the chunk's entries: each pair its alive tiles, row-major, at the
 // scanned offset; pairs follow the depth order, so the chunk's entries are in
-// the same relative order as in the complete lists.
+// the same relative order as in the complete lists.  A pair whose rectangle
+// is small is written by its own thread; larger ones are queued in LDS and
+// written by a whole wave, 64 tiles per step, with ballot compaction, so a
+// screen-sized splat neither serialises a wave nor scatters its stores.
+constexpr int kSmallRect = 32;
+
 __global__ __launch_bounds__(256) void chunk_write_kernel(
     const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
     const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
@@ -607,25 +612,64 @@ __global__ __launch_bounds__(256) void chunk_write_kernel(
     const uint32_t* __restrict__ pcnt, const uint32_t* __restrict__ poff,
     const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t p = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= hi || *chunk_n == 0) return;
-  uint32_t k = pcnt[p - lo];
-  if (k == 0) return;
-  uint32_t m = order[p];
-  if (m >= (uint64_t)M) m = 0;
-  const ushort4 r = drect[p];
-  const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
-  const uint32_t* S = sat + ci.tile_off;
-  int64_t dst = *chunk_base + poff[p - lo];
-  for (int ty = r.y; ty <= r.w && k > 0; ++ty) {
-    if (sat_query(S, ci.GX, r.x, ty, r.z, ty) == 0u) continue;
-    const int64_t row = ci.tile_off + (int64_t)ty * ci.GX;
-    for (int tx = r.x; tx <= r.z; ++tx) {
-      if (alive[row + tx]) {
-        keys[dst] = (uint32_t)(row + tx);
-        vals[dst] = m;
-        ++dst;
-        --k;
+  __shared__ int64_t s_big[256];
+  __shared__ int s_nbig;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (*chunk_n == 0) return;
+  if (tid == 0) s_nbig = 0;
+  __syncthreads();
+  const int64_t p = lo + (int64_t)blockIdx.x * 256 + tid;
+  const int64_t base = *chunk_base;
+  if (p < hi) {
+    uint32_t k = pcnt[p - lo];
+    if (k > 0) {
+      const ushort4 r = drect[p];
+      const int area = (r.z - r.x + 1) * (r.w - r.y + 1);
+      if (area > kSmallRect) {
+        s_big[atomicAdd(&s_nbig, 1)] = p;
+      } else {
+        uint32_t m = order[p];
+        if (m >= (uint64_t)M) m = 0;
+        const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
+        int64_t dst = base + poff[p - lo];
+        for (int ty = r.y; ty <= r.w && k > 0; ++ty) {
+          const int64_t row = ci.tile_off + (int64_t)ty * ci.GX;
+          for (int tx = r.x; tx <= r.z; ++tx) {
+            if (alive[row + tx]) {
+              keys[dst] = (uint32_t)(row + tx);
+              vals[dst] = m;
+              ++dst;
+              --k;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int nbig = s_nbig;
+  for (int b = wave; b < nbig; b += 4) {
+    const int64_t q = s_big[b];
+    uint32_t m = order[q];
+    if (m >= (uint64_t)M) m = 0;
+    const ushort4 r = drect[q];
+    const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
+    const uint32_t* S = sat + ci.tile_off;
+    int64_t dst = base + poff[q - lo];
+    for (int ty = r.y; ty <= r.w; ++ty) {
+      if (sat_query(S, ci.GX, r.x, ty, r.z, ty) == 0u) continue;
+      const int64_t row = ci.tile_off + (int64_t)ty * ci.GX;
+      for (int x0 = r.x; x0 <= r.z; x0 += 64) {
+        const int tx = x0 + lane;
+        const bool keep = tx <= r.z && alive[row + tx] != 0u;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
+        if (keep) {
+          const int64_t at = dst + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          keys[at] = (uint32_t)(row + tx);
+          vals[at] = m;
+        }
+        dst += __popcll(bal);
       }
     }
   }
