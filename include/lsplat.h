@@ -161,7 +161,8 @@ typedef struct ls_cameras {
  *   proj       [M] 64-byte records: double mean2d[2], double conic[3]
  *              (A, B, C with D'^2 = A dx^2 + 2B dx dy + C dy^2), float rgb[3],
  *              float opacity, 8 bytes padding.
- *   rect       [M] uint16 x4: tile rectangle (tx0, ty0, tx1, ty1) inclusive.
+ *   rect       [M] uint16 x4: tile rectangle (tx0, ty0, tx1, ty1) inclusive;
+ *              (1, 1, 0, 0), an empty rectangle, for a culled pair.
  *   ntiles     [M] uint32: tiles touched (0 = culled).
  *   depth_key  [M] uint32: FP32 bit pattern of camera-space z (0xFFFFFFFF if
  *              culled).

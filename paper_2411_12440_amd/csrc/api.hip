@@ -163,7 +163,6 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   p->chunk_spans = take(8 * K);
   p->alive = take(4 * T);
   p->sat = take(4 * T);
-  p->dcnt = take(4 * M);
   p->drect = take(8 * M);
   if (p->K > 1) {
     p->state = take(32 * (size_t)p->P);

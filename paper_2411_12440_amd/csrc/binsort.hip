@@ -150,8 +150,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, const int64_t* base_dev,
     const int64_t* n_dev, int64_t n_host, int shift, int G, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ tot, const uint32_t* __restrict__ gcnt_src,
-    uint32_t* __restrict__ gcnt_dst, const ushort4* __restrict__ grect_src,
+    const uint32_t* __restrict__ tot, const ushort4* __restrict__ grect_src,
     ushort4* __restrict__ grect_dst) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_wcnt[4][256];
@@ -239,10 +238,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
           const uint32_t val = s_vals[p];
           if (kWriteKeys) keys_out[gpos] = key;
           vals_out[gpos] = val;
-          if (gcnt_dst) {           // per-pair data in the new order
-            gcnt_dst[gpos] = gcnt_src[val];
-            grect_dst[gpos] = grect_src[val];
-          }
+          if (grect_dst) grect_dst[gpos] = grect_src[val];   // per-pair data in the new order
         }
       }
     }
@@ -255,9 +251,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
 // Three-kernel exclusive scan (per-block sums, one block scans the sums, each
 // block rescans its span) over inputs given by an accessor.
 // ---------------------------------------------------------------------------
+// tiles in a rectangle (an empty rectangle marks a culled pair)
+__device__ __forceinline__ uint32_t rect_tiles(ushort4 r) {
+  return (r.z >= r.x && r.w >= r.y) ? (uint32_t)(r.z - r.x + 1) * (uint32_t)(r.w - r.y + 1) : 0u;
+}
+
 struct PairCount {          // tiles touched by the pair at depth position p
-  const uint32_t* dcnt;
-  __device__ int64_t operator()(int64_t p) const { return (int64_t)dcnt[p]; }
+  const ushort4* drect;
+  __device__ int64_t operator()(int64_t p) const { return (int64_t)rect_tiles(drect[p]); }
 };
 
 struct SpanCount {
@@ -580,17 +581,17 @@ __device__ __forceinline__ uint32_t sat_query(const uint32_t* S, int GX, int x0,
 // Chunk c of the depth order (pair positions [lo, hi)): for each pair the
 // number of alive tiles in its rectangle.
 __global__ __launch_bounds__(256) void chunk_count_kernel(
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ dcnt,
-    const ushort4* __restrict__ drect, const CamInfo* __restrict__ cams, int C, int64_t M,
-    int64_t lo, int64_t hi, const uint32_t* __restrict__ sat, const int32_t* __restrict__ flags,
+    const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
+    const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
+    const uint32_t* __restrict__ sat, const int32_t* __restrict__ flags,
     uint32_t* __restrict__ pcnt) {
   const int64_t p = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= hi) return;
   uint32_t k = 0;
-  if (flags[0] == 0 && dcnt[p] != 0) {
+  const ushort4 r = drect[p];
+  if (flags[0] == 0 && rect_tiles(r) != 0) {
     uint32_t m = order[p];
     if (m >= (uint64_t)M) m = 0;
-    const ushort4 r = drect[p];
     const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
     k = sat_query(sat + ci.tile_off, ci.GX, r.x, r.y, r.z, r.w);
   }
@@ -721,8 +722,7 @@ template <bool kIdent, bool kWriteKeys>
 hipError_t radix_pass(const char* const names[3], const uint32_t* kin, const uint32_t* vin,
                       uint32_t* kout, uint32_t* vout, const int64_t* base_dev,
                       const int64_t* n_dev, int64_t n_host, int shift, int G, uint32_t* hist,
-                      uint32_t* tot, hipStream_t s, const uint32_t* gcnt_src = nullptr,
-                      uint32_t* gcnt_dst = nullptr, const ushort4* grect_src = nullptr,
+                      uint32_t* tot, hipStream_t s, const ushort4* grect_src = nullptr,
                       ushort4* grect_dst = nullptr) {
   {
     ProfScope ps(names[0], s);
@@ -737,7 +737,7 @@ hipError_t radix_pass(const char* const names[3], const uint32_t* kin, const uin
     ProfScope ps(names[2], s);
     hipLaunchKernelGGL((radix_downsweep<kIdent, kWriteKeys>), dim3(G), dim3(kSortThreads), 0, s,
                        kin, vin, kout, vout, base_dev, n_dev, n_host, shift, G, hist, tot,
-                       gcnt_src, gcnt_dst, grect_src, grect_dst);
+                       grect_src, grect_dst);
   }
   return hipGetLastError();
 }
@@ -796,7 +796,6 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
   int64_t* n_isect = (int64_t*)(ws + p.lay.n_isect);
   int64_t* isect_off = (int64_t*)(ws + p.lay.isect_off);
   uint32_t* order = (uint32_t*)(ws + p.lay.order);
-  const uint32_t* ntiles = (const uint32_t*)(ws + p.lay.ntiles);
   const uint32_t* dkey = (const uint32_t*)(ws + p.lay.depth_key);
   int64_t* chunk_base = (int64_t*)(ws + p.lay.chunk_base);
   int64_t* chunk_n = (int64_t*)(ws + p.lay.chunk_n);
@@ -819,8 +818,7 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
                                      tot, s)))
       return e;
     if ((e = radix_pass<false, false>(kPreNames, kB, vB, nullptr, order, nullptr, nullptr, M, 24,
-                                      G, hist, tot, s, ntiles, (uint32_t*)(ws + p.dcnt),
-                                      (const ushort4*)(ws + p.lay.rect),
+                                      G, hist, tot, s, (const ushort4*)(ws + p.lay.rect),
                                       (ushort4*)(ws + p.drect))))
       return e;
   }
@@ -828,7 +826,7 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
   {
     int64_t* part = (int64_t*)(ws + p.scan_part);
     const int B = scan_blocks_for(M);
-    PairCount in{(const uint32_t*)(ws + p.dcnt)};
+    PairCount in{(const ushort4*)(ws + p.drect)};
     // span owners serve the complete-list key generation only
     PairOffsets out{isect_off, (uint32_t*)(ws + p.span_owner), p.K == 1 ? p.n_spans : 0,
                     part + B};
@@ -875,7 +873,6 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
     int32_t* flags = (int32_t*)(ws + p.lay.flags);
     uint32_t* pcnt = (uint32_t*)(ws + p.span_cnt);
     uint32_t* poff = (uint32_t*)(ws + p.span_off);
-    const uint32_t* dcnt = (const uint32_t*)(ws + p.dcnt);
     const ushort4* drect = (const ushort4*)(ws + p.drect);
     uint32_t *k0, *v0;
     keygen_targets(p, ws, &k0, &v0);
@@ -884,8 +881,8 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
     {
       ProfScope ps("chunk_count", s);
       hipLaunchKernelGGL(alive_sat_kernel, dim3(p.C), dim3(256), 0, s, cams, alive, sat);
-      hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(256), 0, s, order, dcnt, drect, cams,
-                         p.C, M, lo, hi, sat, flags, pcnt);
+      hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams, p.C,
+                         M, lo, hi, sat, flags, pcnt);
     }
     {
       int64_t* part = (int64_t*)(ws + p.scan_part);

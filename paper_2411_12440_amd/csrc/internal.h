@@ -61,7 +61,7 @@ struct Plan {
   // scratch sub-allocations (byte offsets from the workspace base)
   size_t sort_keys_b = 0, sort_vals_b = 0, pre_keys_a = 0, pre_keys_b = 0, pre_vals_a = 0, pre_vals_b = 0,
          hist = 0, digit_tot = 0, scan_part = 0, span_owner = 0, span_cnt = 0, span_off = 0,
-         chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, dcnt = 0, drect = 0;
+         chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, drect = 0;
   int64_t n_spans = 0;        // entries of span_owner: ceil(cap / kKeygenSpan) + 1
   int32_t K = 1;              // depth chunks
   std::vector<int64_t> chunk_pos;   // [K + 1] pair positions in depth order
@@ -88,6 +88,15 @@ constexpr int kMaxScanBlocks = 1024;
 template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ float dpp_move(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+
+// Sum over each row of 16 lanes; every lane receives its row's sum.
+__device__ __forceinline__ float row_sum16(float x) {
+  x += dpp_move<0x128>(x);        // row_ror:8
+  x += dpp_move<0x124>(x);        // row_ror:4
+  x += dpp_move<0x122>(x);        // row_ror:2
+  x += dpp_move<0x121>(x);        // row_ror:1
+  return x;
 }
 
 __device__ __forceinline__ float wave_sum_to_lane63(float x) {

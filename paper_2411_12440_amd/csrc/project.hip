@@ -138,7 +138,7 @@ __device__ __noinline__ BinOut bin_fp32(float mx_, float my_, float mz_, float s
   bool keep = finite && (t2 > near_z) && (t2 < far_z) && (xlo <= xhi) && (ylo <= yhi);
   BinOut o;
   if (!keep) {
-    o.rect = make_ushort4(0, 0, 0, 0);
+    o.rect = make_ushort4(1, 1, 0, 0);   // empty rectangle
     o.ntiles = 0;
     o.dkey = 0xFFFFFFFFu;
     return o;
