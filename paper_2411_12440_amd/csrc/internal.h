@@ -90,13 +90,45 @@ __device__ __forceinline__ float dpp_move(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
 }
 
-// Sum over each row of 16 lanes; every lane receives its row's sum.
-__device__ __forceinline__ float row_sum16(float x) {
+// Sums of 8 values over the wave at once.  Each step halves the lanes a value
+// spans while pairing values up, so that eight wave-wide sums cost 18
+// instructions rather than 48:
+//   1. v_permlane32_swap pairs (v0,v1) ... (v6,v7): after the add, lanes 0..31
+//      hold partial sums of the first value of the pair, lanes 32..63 of the
+//      second;
+//   2. v_permlane16_swap pairs the four results: each 16-lane row then holds
+//      one value (rows: v0 v2 v1 v3 and v4 v6 v5 v7);
+//   3. a row rotation by 8 and a select pack the two registers into one, each
+//      8-lane group holding one value;
+//   4. a half-row mirror and two quad permutations finish each group's sum in
+//      its first lane.
+// Result: lane 8g (g = 0..7) holds the sum of v[wave_sum8_field(g)]; other
+// lanes hold partial sums.  All lanes must be active.
+__host__ __device__ __forceinline__ int wave_sum8_field(int g) {   // 3-bit reversal
+  return ((g & 1) << 2) | (g & 2) | ((g >> 2) & 1);
+}
+
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float wave_sum8(const float* v, int lane) {
+  const float a = swap32_add(v[0], v[1]), b = swap32_add(v[2], v[3]);
+  const float c = swap32_add(v[4], v[5]), d = swap32_add(v[6], v[7]);
+  float x = swap16_add(a, b), y = swap16_add(c, d);
   x += dpp_move<0x128>(x);        // row_ror:8
-  x += dpp_move<0x124>(x);        // row_ror:4
-  x += dpp_move<0x122>(x);        // row_ror:2
-  x += dpp_move<0x121>(x);        // row_ror:1
-  return x;
+  y += dpp_move<0x128>(y);
+  float z = (lane & 8) ? y : x;
+  z += dpp_move<0x141>(z);        // row_half_mirror
+  z += dpp_move<0x4E>(z);         // quad_perm [2,3,0,1]
+  z += dpp_move<0xB1>(z);         // quad_perm [1,0,3,2]
+  return z;
 }
 
 __device__ __forceinline__ float wave_sum_to_lane63(float x) {

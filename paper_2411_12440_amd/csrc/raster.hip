@@ -99,7 +99,6 @@ struct Stage {
   double qa[NT], qb[NT], qc[NT], qd[NT], qe[NT], qf[NT];
   double ox[NT], oy[NT];     // centre relative to the tile's first pixel centre
   float r[NT], g[NT], b[NT], o[NT];
-  float ylo[NT], yhi[NT];    // rows of the tile the support ellipse can reach
   int32_t pos[NT];           // position in the tile list
   uint32_t m[NT];            // pair id
   int32_t wcount[NT / 64];
@@ -180,10 +179,6 @@ __device__ __forceinline__ int stage_batch(Stage<TW * TH>& st, const uint32_t* _
     st.qf[k] = ox * u + oy * v;
     st.ox[k] = ox;
     st.oy[k] = oy;
-    // vertical half-extent of D'^2 < lam2: lambda sqrt(Sigma_yy), Sigma_yy = A / det(conic)
-    const double yr = sqrt(lam2 * A / (A * C - B * B)) * (1.0 + 1e-6) + 1e-6;
-    st.ylo[k] = (float)(oy - yr) - 1e-3f;
-    st.yhi[k] = (float)(oy + yr) + 1e-3f;
     st.r[k] = rec.r;
     st.g[k] = rec.g;
     st.b[k] = rec.b;
@@ -229,8 +224,6 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
   const double lx = (double)lxi, ly = (double)lyi;
   const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
-  // the pixel rows of this wave (TW x (64 / TW) pixels)
-  const float band_lo = (float)((tid >> 6) * (64 / TW)), band_hi = band_lo + (float)(64 / TW - 1);
   const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
 
   double T = 1.0, cr = 0.0, cg = 0.0, cb = 0.0;
@@ -252,7 +245,6 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
                                         prefix + p0 + tid, x0c, y0c, rp.lam2);
     if (!done) {
       for (int k = 0; k < cnt; ++k) {
-        if (st.yhi[k] < band_lo || st.ylo[k] > band_hi) continue;   // uniform per wave
         const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
                                     lx, ly, lx2, lxy, ly2);
         if (!(q < rp.lam2)) continue;
@@ -301,7 +293,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
   __shared__ Stage<NT> st;
-  __shared__ float s_acc[kGrad2d][NT];
+  __shared__ float s_acc[NT][kGrad2d];   // per staged entry; odd stride, no bank conflicts
   __shared__ int32_t s_max[NW];
   __shared__ int64_t s_segbase[kMaxDepthChunks];
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
@@ -317,8 +309,6 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
   const double lx = (double)lxi, ly = (double)lyi;
   const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
-  // the pixel rows of this wave (TW x (64 / TW) pixels)
-  const float band_lo = (float)((tid >> 6) * (64 / TW)), band_hi = band_lo + (float)(64 / TW - 1);
   // the tile's list: its segments of every chunk, in chunk order
   if (tid == 0) {
     int32_t pre = 0;
@@ -374,7 +364,6 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
     for (int i = tid; i < kGrad2d * NT; i += NT) (&s_acc[0][0])[i] = 0.f;
     __syncthreads();
     for (int k = cnt - 1; k >= 0; --k) {
-      if (st.yhi[k] < band_lo || st.ylo[k] > band_hi) continue;     // uniform per wave
       float gv[kGrad2d];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.f;
@@ -440,13 +429,13 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
           }
         }
       }
-      // sums over each 16-lane row (all lanes active here), one LDS add per row
+      // wave-wide sums (all lanes active here), one LDS add per wave
       if (__builtin_amdgcn_ballot_w64(contrib) != 0ull) {
-#pragma unroll
-        for (int f = 0; f < kGrad2d; ++f) {
-          const float sum = row_sum16(gv[f]);
-          if ((lane & 15) == 0 && sum != 0.f) atomicAdd(&s_acc[f][k], sum);
-        }
+        static_assert(kGrad2d == 9, "eight fields summed together, one alone");
+        const float s8 = wave_sum8(gv, lane);
+        if ((lane & 7) == 0 && s8 != 0.f) atomicAdd(&s_acc[k][wave_sum8_field(lane >> 3)], s8);
+        const float s1 = wave_sum_to_lane63(gv[8]);
+        if (lane == 63 && s1 != 0.f) atomicAdd(&s_acc[k][8], s1);
       }
     }
     __syncthreads();
@@ -454,7 +443,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
       const int64_t m = (int64_t)st.m[tid];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) {
-        const float v = s_acc[f][tid];
+        const float v = s_acc[tid][f];
         if (v != 0.f) unsafeAtomicAdd(grad2d + (int64_t)f * M + m, v);
       }
     }
