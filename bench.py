@@ -63,12 +63,13 @@ def make_workload(n_splats, views):
 
 
 # --------------------------------------------------------------------------
-# algorithmic cost of each kernel per launch ("Roofline")
+# algorithmic cost of each kernel per step: what the method must move or
+# compute, independent of how the kernels do it
 # --------------------------------------------------------------------------
 
 def kernel_cost(name, w):
     """(bound, amount per launch, unit) for the kernels we can price."""
-    N, M, n, K, Q = w["N"], w["M"], w["n_built"], w["K"], w["Q"]
+    N, M, n, K, Q, Qc = w["N"], w["M"], w["n_built"], w["K"], w["Q"], w["Qc"]
     splat_bytes = 44 + 12 * K
     if name == "tilesort_downsweep":
         return "hbm", 16.0 * n, "B"
@@ -84,10 +85,17 @@ def kernel_cost(name, w):
         return "hbm", float(splat_bytes) * N + 80.0 * M, "B"
     if name == "project_bwd":
         return "hbm", float(splat_bytes - 4) * N + 36.0 * M + float(splat_bytes) * N, "B"
-    if name in ("raster_fwd", "raster_bwd"):
-        # FP64 quadratic form of every (pixel, splat) pair up to the pixel's
-        # last contributor: 9 flops (2 sub, 3 mul, 2 fma)
-        return "alu", 9.0 * Q, "flop"
+    # Compositing: every (pixel, splat) pair up to the pixel's last contributor
+    # (Q of them) evaluates D'^2 (5 FMA = 10 flops); each contributing pair (Qc)
+    # then costs 13 flops forward (sqrt, alpha, T (1 - alpha), alpha T, three
+    # colour FMA) and 65 backward (alpha and T_i recovered, two 3-dot products,
+    # dL/dalpha, suffix update, colour / opacity / distance / AGS weight,
+    # dL/dq, the two gradient directions, mean and conic terms, and one add
+    # per gradient field for the sum over pixels).  sqrt and exp count 1.
+    if name == "raster_fwd":
+        return "alu", 10.0 * Q + 13.0 * Qc, "flop"
+    if name == "raster_bwd":
+        return "alu", 10.0 * Q + 65.0 * Qc, "flop"
     return None
 
 
@@ -178,8 +186,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this rasterizer runs on one GPU; multi-GPU runs are not part of this "
-              "build (see DESIGN.md for how the path would shard across GPUs).", file=sys.stderr)
+        print("bench.py: this rasterizer runs on one GPU.  Across GPUs the views would be "
+              "sharded, with one all-reduce of the splat gradients per step; that path is not "
+              "built, so only --gpus 1 runs.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -232,6 +241,8 @@ def main():
     assert not rast.overflowed()
     last = rast.last.to(torch.int64)
     Q = int(last.sum().item())
+    Qc = rast.contributions()
+    chunk_entries = [int(v) for v in np.diff(rast.lists()[0])]
     value = P / (ms_batched * 1e-3) / 1e6
     log(f"bench: batched {ms_batched:.3f} ms/step, {value:.1f} Mpx/s")
 
@@ -277,11 +288,18 @@ def main():
         del views
 
     # ---- roofline of the dominant kernel --------------------------------------
-    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q)
+    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q, Qc=Qc)
     kernels = []
     for name, launches, total in ktimes:
-        kernels.append(dict(kernel=name, launches=launches, avg_ms=round(total / launches, 4),
-                            total_ms_per_step=round(total / args.steps, 4)))
+        row = dict(kernel=name, launches=launches, avg_ms=round(total / launches, 4),
+                   total_ms_per_step=round(total / args.steps, 4))
+        cost = kernel_cost(name, w)
+        if cost is not None:       # fraction of its roofline over the step
+            bound, amount, _ = cost
+            rate = amount / (total / args.steps * 1e-3)
+            row["frac"] = round(rate / (HBM_PEAK_GBS * 1e9 if bound == "hbm"
+                                        else FP64_VEC_PEAK_TFLOPS * 1e12), 4)
+        kernels.append(row)
     roof = None
     if kernels:
         dom = kernels[0]
@@ -289,7 +307,7 @@ def main():
         if cost is not None:
             bound, amount, unit = cost
             launches_per_step = dom["launches"] / args.steps
-            per_launch = amount / launches_per_step if bound == "hbm" else amount
+            per_launch = amount / launches_per_step
             sec = dom["avg_ms"] * 1e-3
             if bound == "hbm":
                 achieved = per_launch / sec / 1e9
@@ -324,7 +342,9 @@ def main():
                                "radius-4 sphere, fwd+bwd, batched",
                    "views": cams.n, "pixels_per_step": P, "n_isect": n_isect,
                    "entries_built": n_built, "depth_chunks": args.depth_chunks,
-                   "pairs_to_last": Q, "ags": bool(args.ags), "tile": "16x16",
+                   "chunk_entries": chunk_entries,
+                   "pairs_to_last": Q, "contributing_pairs": Qc, "ags": bool(args.ags),
+                   "tile": "16x16",
                    "parallelism": "single GPU"},
         "per_view": per_view,
         "roofline": roof,

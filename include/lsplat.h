@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 110
+#define LSPLAT_VERSION 120
 
 typedef enum {
   LS_OK = 0,
@@ -122,13 +122,20 @@ typedef struct ls_splats {
   const float* sh;
 } ls_splats;
 
-/* Gradients w.r.t. the ls_splats fields, same shapes (written, not added). */
+/*
+ * Gradients w.r.t. the ls_splats fields, same shapes (written, not added).
+ * mean2d_norm  optional (NULL to skip) [M] per (camera, splat) pair: the
+ *              Euclidean norm of dL/d(projected centre) in pixels, the
+ *              per-view statistic that 3DGS-style densification accumulates;
+ *              0 for a pair that received no gradient.
+ */
 typedef struct ls_grads {
   float* means;
   float* scales;
   float* quats;
   float* opacity;
   float* sh;
+  float* mean2d_norm;
 } ls_grads;
 
 /*
@@ -182,12 +189,16 @@ typedef struct ls_cameras {
  *              capacity (the composite is then incomplete: grow the capacity
  *              to at least n_isect and run again).
  *   grad2d     [9][M] float: per-pair 2D gradient sums (backward), field-major.
+ *   tile_contrib [T] uint32: per tile, the (pixel, splat) pairs that
+ *              contributed to the composite in the last ls_rasterize_fwd call
+ *              (alpha >= alpha_min, before the pixel stopped); the backward
+ *              pass visits the same set.
  */
 typedef struct ls_layout {
   int64_t n_pairs, n_tiles, n_pixels, capacity, n_chunks;
   size_t total_bytes;
   size_t cams, proj, rect, ntiles, depth_key, order, isect_off, keys, vals, ranges,
-      n_isect, chunk_base, chunk_n, flags, grad2d;
+      n_isect, chunk_base, chunk_n, flags, grad2d, tile_contrib;
   size_t scratch;   /* library-internal (sort buffers, histograms, state) */
 } ls_layout;
 
@@ -260,12 +271,17 @@ ls_status ls_rasterize_fwd(const ls_config* cfg, const ls_cameras* cams, void* w
  * chain rule through the projection and sums over cameras.
  * final_T, last  from the forward call on the same workspace and settings.
  * dL_dimage      [sum_c 3 H_c W_c] upstream gradient.
+ * dL_dalpha      optional (NULL = zero) [P] upstream gradient of each pixel's
+ *                accumulated opacity 1 - T_final.  It enters as a fourth
+ *                channel whose splat colours are 0 and whose background is -1:
+ *                dL/dalpha_i gains dL_dalpha * T_final / (1 - alpha_i).
  * grads          out: written (not accumulated) for every splat.
  */
 ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* splats,
                            const ls_cameras* cams, void* ws, size_t ws_bytes,
                            int64_t isect_capacity, const float* final_T, const int32_t* last,
-                           const float* dL_dimage, const ls_grads* grads, void* stream);
+                           const float* dL_dimage, const float* dL_dalpha,
+                           const ls_grads* grads, void* stream);
 
 /*
  * Kernel timing (tracing).  While enabled, every kernel the library enqueues

@@ -108,10 +108,12 @@ def composite_tile(ids, px, py, mean2d, conic, opac, rgb, cfg, want_pairs=False)
     return out
 
 
-def reverse_tile(res, G, mean2d, conic, opac, rgb, cfg, n_splats):
+def reverse_tile(res, G, mean2d, conic, opac, rgb, cfg, n_splats, GA=None):
     """Reverse pass over one tile's contributing pairs.
 
-    G [P,3] = dL/d(image) at the tile's pixels.  Returns per-splat arrays
+    G [P,3] = dL/d(image) at the tile's pixels; GA [P] (optional) = dL/dA for
+    the accumulated opacity A = 1 - T_final = 1 - prod_i (1 - alpha_i), whose
+    derivative w.r.t. alpha_i is T_final / (1 - alpha_i).  Returns per-splat arrays
     (length n_splats) g_rgb [.,3], g_opac [.], g_conic [.,3] (w.r.t. A, B, C),
     g_mean2d [.,2]."""
     g_rgb = np.zeros((n_splats, 3))
@@ -139,6 +141,8 @@ def reverse_tile(res, G, mean2d, conic, opac, rgb, cfg, n_splats):
     Gp = G[p]
     dL_drgb = Gp * (alpha * Tb)[:, None]
     dL_dalpha = Tb * np.sum(Gp * c_i, axis=1) - np.sum(Gp * S, axis=1) / (1.0 - alpha)
+    if GA is not None:
+        dL_dalpha = dL_dalpha + np.asarray(GA, np.float64)[p] * res["T"][p] / (1.0 - alpha)
     raw, L, D = pr["raw"][order], pr["L"][order], pr["D"][order]
     unclamped = raw < cfg.alpha_max
     dL_do = np.where(unclamped, L * dL_dalpha, 0.0)

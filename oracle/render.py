@@ -138,11 +138,14 @@ def render_forward(scene, scene_off, cams, cfg, tiles=None, want_pairs=False):
     return fw
 
 
-def render_backward(fw, scene, cams, dL_dimage):
+def render_backward(fw, scene, cams, dL_dimage, dL_dalpha=None):
     """Reverse pass of ``render_forward(..., want_pairs=True)`` over the tiles
-    it composited.  dL_dimage has the image layout.  Returns a dict of
-    gradients w.r.t. means [N,3], scales [N,3], quats [N,4], opacity [N],
-    sh [N,K,3], plus the per-pair 2D gradients (for staged comparison)."""
+    it composited.  dL_dimage has the image layout; dL_dalpha (optional, one
+    value per pixel in the final_T layout) is the upstream gradient of the
+    accumulated opacity 1 - T_final.  Returns a dict of gradients w.r.t.
+    means [N,3], scales [N,3], quats [N,4], opacity [N], sh [N,K,3], plus the
+    per-pair 2D gradients (for staged comparison) and mean2d_norm [M], the
+    Euclidean norm of each pair's dL/d(projected centre)."""
     cfg, lay = fw.cfg, fw.lay
     N = scene.n
     K = scene.sh.shape[1]
@@ -165,7 +168,11 @@ def render_backward(fw, scene, cams, dL_dimage):
             local = res["pix"] - int(lay.pix_off[c])
             G = np.stack([np.asarray(dL_dimage[img_base + ch * W * H + local], np.float64)
                           for ch in range(3)], axis=1)
-            r = composite.reverse_tile(res, G, p["mean2d"], p["conic"], opac, p["rgb"], cfg, n_c)
+            GA = None
+            if dL_dalpha is not None:
+                GA = np.asarray(dL_dalpha[int(lay.pix_off[c]) + local], np.float64)
+            r = composite.reverse_tile(res, G, p["mean2d"], p["conic"], opac, p["rgb"], cfg, n_c,
+                                       GA)
             for a, b in zip(acc, r):
                 a += b
         m0, m1 = int(lay.pair_off[c]), int(lay.pair_off[c + 1])
@@ -180,4 +187,5 @@ def render_backward(fw, scene, cams, dL_dimage):
         out["opacity"][sl] += acc[1]
         out["sh"][sl] += gsh
     out["pair"] = g2
+    out["mean2d_norm"] = np.sqrt(np.sum(g2["mean2d"] ** 2, axis=1))
     return out

@@ -42,7 +42,7 @@ class Splats(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("mean2d_norm", C.c_void_p)]
 
 
 class Cams(C.Structure):
@@ -59,7 +59,7 @@ class Layout(C.Structure):
                 ("isect_off", C.c_size_t), ("keys", C.c_size_t), ("vals", C.c_size_t),
                 ("ranges", C.c_size_t), ("n_isect", C.c_size_t), ("chunk_base", C.c_size_t),
                 ("chunk_n", C.c_size_t), ("flags", C.c_size_t), ("grad2d", C.c_size_t),
-                ("scratch", C.c_size_t)]
+                ("tile_contrib", C.c_size_t), ("scratch", C.c_size_t)]
 
 
 class KernelTime(C.Structure):
@@ -84,7 +84,8 @@ def _load() -> C.CDLL:
         "ls_rasterize_fwd": ([P(Config), P(Cams), C.c_void_p, C.c_size_t, C.c_int64, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
         "ls_rasterize_bwd": ([P(Config), P(Splats), P(Cams), C.c_void_p, C.c_size_t, C.c_int64,
-                              C.c_void_p, C.c_void_p, C.c_void_p, P(Grads), C.c_void_p], C.c_int),
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(Grads), C.c_void_p],
+                             C.c_int),
         "ls_profile_enable": ([C.c_int], C.c_int),
         "ls_profile_read": ([P(KernelTime), C.c_int, P(C.c_int), C.c_int], C.c_int),
     }
@@ -149,8 +150,9 @@ def splats_struct(n, means, scales, quats, opacity, sh) -> Splats:
     return Splats(n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh))
 
 
-def grads_struct(means, scales, quats, opacity, sh) -> Grads:
-    return Grads(_ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh))
+def grads_struct(means, scales, quats, opacity, sh, mean2d_norm=None) -> Grads:
+    return Grads(_ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh),
+                 _ptr(mean2d_norm))
 
 
 def ls_version() -> int:
@@ -185,10 +187,11 @@ def ls_rasterize_fwd(cfg, cams: CamerasHost, ws, capacity, image, final_T, last,
 
 
 def ls_rasterize_bwd(cfg, splats: Splats, cams: CamerasHost, ws, capacity, final_T, last,
-                     dL_dimage, grads: Grads, stream=None):
+                     dL_dimage, dL_dalpha, grads: Grads, stream=None):
     _check(LIB.ls_rasterize_bwd(C.byref(cfg), C.byref(splats), C.byref(cams.c), _ptr(ws),
                                 ws.numel(), capacity, _ptr(final_T), _ptr(last),
-                                _ptr(dL_dimage), C.byref(grads), _stream(stream)))
+                                _ptr(dL_dimage), _ptr(dL_dalpha), C.byref(grads),
+                                _stream(stream)))
 
 
 def ls_profile_enable(on: bool = True):

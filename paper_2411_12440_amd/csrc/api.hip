@@ -132,6 +132,7 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   L.chunk_n = take(8 * K);
   L.flags = take(64);
   L.grad2d = take(4 * kGrad2d * M);
+  L.tile_contrib = take(4 * T);
   L.scratch = off;
   p->pre_keys_a = take(4 * M);
   p->pre_keys_b = take(4 * M);
@@ -264,8 +265,8 @@ ls_status ls_rasterize_fwd(const ls_config* cfg, const ls_cameras* cams, void* w
 
 ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* sp, const ls_cameras* cams,
                            void* ws, size_t ws_bytes, int64_t cap, const float* final_T,
-                           const int32_t* last, const float* dL_dimage, const ls_grads* g,
-                           void* stream) {
+                           const int32_t* last, const float* dL_dimage, const float* dL_dalpha,
+                           const ls_grads* g, void* stream) {
   Plan p;
   ls_status st = make_plan(cfg, cams, cap, &p);
   if (st != LS_OK) return st;
@@ -274,8 +275,8 @@ ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* sp, const ls_c
   if (!final_T || !last || !dL_dimage) return fail(LS_ERR_INVALID_ARG, "final_T/last/dL_dimage is NULL");
   if (!g || (p.N > 0 && (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh)))
     return fail(LS_ERR_INVALID_ARG, "gradient pointer is NULL");
-  hipError_t e = launch_raster_bwd(p, cfg, sp, (char*)ws, final_T, last, dL_dimage, g,
-                                   (hipStream_t)stream);
+  hipError_t e = launch_raster_bwd(p, cfg, sp, (char*)ws, final_T, last, dL_dimage, dL_dalpha,
+                                   g, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "rasterize_bwd");
   return LS_OK;
 }

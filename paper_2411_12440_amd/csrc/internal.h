@@ -163,6 +163,6 @@ hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_spla
                               const ls_grads* g, hipStream_t s);
 hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                              const float* final_T, const int32_t* last, const float* dL_dimage,
-                             const ls_grads* g, hipStream_t s);
+                             const float* dL_dalpha, const ls_grads* g, hipStream_t s);
 
 }  // namespace lsplat

@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
     const float* __restrict__ scales, const float* __restrict__ quats,
     const float* __restrict__ sh, float eps, float clip, const float* __restrict__ grad2d,
     int64_t M, float* __restrict__ g_means, float* __restrict__ g_scales,
-    float* __restrict__ g_quats, float* __restrict__ g_opac) {
+    float* __restrict__ g_quats, float* __restrict__ g_opac, float* __restrict__ g_m2norm) {
   int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
   if (i >= N) return;
   double mu[3], s[3], q[4];
@@ -394,6 +394,7 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
       g2[f] = grad2d[(int64_t)f * M + m];
       any |= (g2[f] != 0.f);
     }
+    if (g_m2norm) g_m2norm[m] = sqrtf(g2[0] * g2[0] + g2[1] * g2[1]);
     if (!any) continue;
     Geo g;
     geo_compute(ci, mu[0], mu[1], mu[2], s[0], s[1], s[2], q[0], q[1], q[2], q[3], clip, eps, g);
@@ -603,7 +604,7 @@ hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_spla
       hipLaunchKernelGGL(project_bwd_kernel<D>, grid, dim3(kProjThreads), 0, s, cams, p.C, p.N,   \
                          sp->means, sp->scales, sp->quats, sp->sh, cfg->eps2d, cfg->clip,         \
                          (const float*)(ws + p.lay.grad2d), p.M, gr->means, gr->scales,           \
-                         gr->quats, gr->opacity);                                                 \
+                         gr->quats, gr->opacity, gr->mean2d_norm);                                \
     }                                                                                              \
     {                                                                                              \
       ProfScope ps("project_bwd_sh", s);                                                           \

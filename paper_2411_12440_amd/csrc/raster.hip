@@ -199,9 +199,11 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
     int c, int K, const int64_t* __restrict__ chunk_base, const uint32_t* __restrict__ vals,
     const ProjRec* __restrict__ proj, int64_t M, int batch, RasterParams rp,
     double4* __restrict__ state, uint8_t* __restrict__ done_px, uint32_t* __restrict__ alive,
-    float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ last) {
+    float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ last,
+    uint32_t* __restrict__ tile_contrib) {
   constexpr int NT = TW * TH;
   __shared__ Stage<NT> st;
+  __shared__ uint32_t s_cnt[NT / 64];
   const int tid = threadIdx.x;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   if (c > 0 && alive[tile] == 0u) return;
@@ -228,6 +230,7 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
 
   double T = 1.0, cr = 0.0, cg = 0.0, cb = 0.0;
   int32_t lastc = 0;
+  uint32_t ncon = 0;
   bool done = !inside;
   if (c > 0 && inside) {
     const double4 sv = state[pix];
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
         cb = fma((double)st.b[k], w, cb);
         T = Tn;
         lastc = st.pos[k] + 1;
+        ++ncon;
       }
     }
   }
@@ -272,6 +276,16 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
     image[ib + 2 * plane] = (float)(cb + T * (double)rp.bg2);
     final_T[pix] = (float)T;
     last[pix] = lastc;
+  }
+  // contributing pairs of the tile (a statistic for throughput accounting)
+  for (int d = 32; d > 0; d >>= 1) ncon += __shfl_xor(ncon, d, 64);
+  if ((tid & 63) == 0) s_cnt[tid >> 6] = ncon;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += s_cnt[w];
+    tile_contrib[tile] = (c > 0 ? tile_contrib[tile] : 0u) + t;
   }
   if (K > 1 && c < K - 1) {
     if (inside) {
@@ -289,7 +303,8 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
     int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
     RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
-    const float* __restrict__ dL_dimage, float* __restrict__ grad2d) {
+    const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
+    float* __restrict__ grad2d) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
   __shared__ Stage<NT> st;
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   __syncthreads();
   const int64_t len = s_segpre[K];
 
-  double T = 1.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
+  double T = 1.0, G0 = 0.0, G1 = 0.0, G2 = 0.0, GA = 0.0;
   int32_t mylast = 0;
   if (inside) {
     const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
@@ -335,9 +350,13 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
     G0 = dL_dimage[ib];
     G1 = dL_dimage[ib + plane];
     G2 = dL_dimage[ib + 2 * plane];
+    if (dL_dalpha) GA = dL_dalpha[pix];
   }
   // suffix colour behind the current splat, starting with the background term
   double S0 = T * (double)rp.bg0, S1 = T * (double)rp.bg1, S2 = T * (double)rp.bg2;
+  // the accumulated opacity 1 - T_final as a fourth channel: splat colours 0,
+  // background -1, so its suffix term is the constant -T_final
+  const double GSa = -GA * T;
   // tile-wide maximum of `last`
   int32_t mx = mylast;
   for (int d = 32; d > 0; d >>= 1) {
@@ -383,7 +402,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
             const double w = e.alpha * Ti;
             const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
             const double GdC = G0 * cr + G1 * cg + G2 * cb;
-            const double GdS = G0 * S0 + G1 * S1 + G2 * S2;
+            const double GdS = G0 * S0 + G1 * S1 + G2 * S2 + GSa;
             const double dLda = Ti * GdC - GdS * inv;
             S0 = fma(cr, w, S0);
             S1 = fma(cg, w, S1);
@@ -489,6 +508,7 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
   const uint32_t* vals = (const uint32_t*)(ws + p.lay.vals);
   const ProjRec* proj = (const ProjRec*)(ws + p.lay.proj);
   double4* state = (double4*)(ws + p.state);
+  uint32_t* tile_contrib = (uint32_t*)(ws + p.lay.tile_contrib);
   uint8_t* done = (uint8_t*)(ws + p.done);
   uint32_t* alive = (uint32_t*)(ws + p.alive);
   RasterParams rp = make_params(cfg);
@@ -507,7 +527,7 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
 #define LS_FWD(TW_, TH_)                                                                           \
   hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
                      p.T, c, p.K, chunk_base, vals, proj, p.M, batch, rp, state, done, alive, image, \
-                     final_T, last)
+                     final_T, last, tile_contrib)
     if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_FWD(16, 16);
     else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_FWD(16, 8);
     else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_FWD(8, 8);
@@ -520,7 +540,7 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
 
 hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                              const float* final_T, const int32_t* last, const float* dL_dimage,
-                             const ls_grads* g, hipStream_t s) {
+                             const float* dL_dalpha, const ls_grads* g, hipStream_t s) {
   float* grad2d = (float*)(ws + p.lay.grad2d);
   const int64_t ng = (int64_t)kGrad2d * p.M;
   if (ng > 0) {
@@ -542,7 +562,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
 #define LS_BWD(TW_, TH_)                                                                         \
   hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
                      p.T, p.K, chunk_base, vals, proj, p.M, batch, rp, final_T, last, dL_dimage, \
-                     grad2d)
+                     dL_dalpha, grad2d)
     if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_BWD(16, 16);
     else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_BWD(16, 8);
     else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_BWD(8, 8);

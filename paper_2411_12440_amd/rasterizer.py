@@ -101,11 +101,14 @@ class Rasterizer:
         B.ls_rasterize_fwd(self.cfg, self.cams, self.ws, self.capacity, self.image,
                            self.final_T, self.last, self._stream(stream))
 
-    def rasterize_bwd(self, sp, dL_dimage, grads, stream=None):
+    def rasterize_bwd(self, sp, dL_dimage, grads, stream=None, dL_dalpha=None):
+        """grads: dict of output tensors (means, scales, quats, opacity, sh and,
+        optionally, mean2d_norm [M])."""
         g = B.grads_struct(grads["means"], grads["scales"], grads["quats"], grads["opacity"],
-                           grads["sh"])
+                           grads["sh"], grads.get("mean2d_norm"))
         B.ls_rasterize_bwd(self.cfg, self._splats(sp), self.cams, self.ws, self.capacity,
-                           self.final_T, self.last, dL_dimage.contiguous(), g,
+                           self.final_T, self.last, dL_dimage.contiguous(),
+                           None if dL_dalpha is None else dL_dalpha.contiguous(), g,
                            self._stream(stream))
 
     def _stream(self, stream):
@@ -129,10 +132,18 @@ class Rasterizer:
             self._alloc(int(grow) + 1024)
         return self.image, self.final_T, self.last
 
-    def backward(self, sp, dL_dimage, stream=None):
+    def backward(self, sp, dL_dimage, stream=None, dL_dalpha=None, mean2d_norm=False):
         grads = {k: torch.empty_like(v) for k, v in sp.items()}
-        self.rasterize_bwd(sp, dL_dimage, grads, stream)
+        if mean2d_norm:
+            grads["mean2d_norm"] = torch.empty(int(self.layout.n_pairs), dtype=torch.float32,
+                                               device=self.device)
+        self.rasterize_bwd(sp, dL_dimage, grads, stream, dL_dalpha)
         return grads
+
+    def contributions(self) -> int:
+        """(pixel, splat) pairs that contributed in the last forward call."""
+        T = int(self.layout.n_tiles)
+        return int(self.view("tile_contrib", torch.int32, T).to(torch.int64).sum().item())
 
 
 class RenderFunction(torch.autograd.Function):

@@ -218,6 +218,23 @@ def compare_grads(grads_gpu, go, scene, rel=REL):
     assert_close("d_sh", grads_gpu["sh"].reshape(K, 3, N).transpose(2, 0, 1), go["sh"], rel)
 
 
+def compare_contributions(rast, fw):
+    """Per-tile counts of contributing (pixel, splat) pairs against the
+    oracle's, on every composited tile with no pixel near a threshold."""
+    import torch
+    T = int(rast.layout.n_tiles)
+    got = rast.view("tile_contrib", torch.int32, T).cpu().numpy().astype(np.int64)
+    checked = 0
+    for gt, res in fw.tile_res.items():
+        if res["flag"].any():
+            continue
+        want = 0 if res["pairs"] is None else len(res["pairs"]["p"])
+        assert got[gt] == want, (gt, got[gt], want)
+        checked += 1
+    say(f"  tile contribution counts equal on {checked} tiles")
+    assert checked > 0
+
+
 def tile_list_oracle(fw, gtile):
     """Plain definition of one tile's list: the pairs whose rect contains the
     tile, ordered by (depth key, pair id)."""

@@ -1,0 +1,185 @@
+"""Parity at the benchmark's full size and launch configuration: 3.2M splats
+with SH degree 3, eight 1920x1080 views on a sphere, AGS on, 16x16 tiles,
+seven depth chunks.  The FP64 oracle cannot composite all 16.6M pixels, so
+the test checks
+
+  * the FP32 binning integers (rect, tiles touched, depth key) of every pair
+    of every view bit for bit, and the depth order and intersection count by
+    their definitions;
+  * a seeded sample of tiles one by one: each tile's list (a prefix of its
+    plain-definition list that reaches the tile's last contributor), the
+    projected records of its splats, the composite (image, final_T, last) and
+    the contribution count;
+  * the gradients of every splat for an upstream gradient that is non-zero on
+    the sampled tiles only (every other splat must receive exactly zero).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import binning, composite, projection
+from oracle.render import layout
+from paper_2411_12440_amd import scenes
+from tests.gpu_helpers import assert_close, cfg_pair, say
+
+pytestmark = pytest.mark.gpu
+
+VIEWS_SAMPLED = (0, 5)
+TILES_PER_VIEW = 6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_benchmark_configuration_sampled():
+    import torch
+    from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
+
+    say("case: full size, 3.2M splats SH3, 8 x 1920x1080, AGS, depth chunks 7")
+    scene, off, cams = scenes.workload(40)
+    N = scene.n
+    ocfg, gkw = cfg_pair(ags=True, depth_chunks=7)
+    sp = scene_to_device(scene)
+    rast = Rasterizer(cams, off, capacity=1 << 24, sh_degree=3, **gkw)
+    rast.forward(sp)
+    torch.cuda.synchronize()
+    assert not rast.overflowed()
+    L = rast.layout
+    M, T = int(L.n_pairs), int(L.n_tiles)
+    lay = layout(off, cams, ocfg)
+    assert M == cams.n * N and T == int(lay.tile_off[-1])
+
+    # -- binning integers of every pair, bit for bit -------------------------
+    g_rect = rast.view("rect", torch.int16, 4 * M).cpu().numpy().view(np.uint16).reshape(M, 4)
+    g_nt = rast.view("ntiles", torch.int32, M).cpu().numpy().view(np.uint32).astype(np.int64)
+    g_dk = rast.view("depth_key", torch.int32, M).cpu().numpy().view(np.uint32)
+    rect = np.zeros((M, 4), np.int64)
+    nt = np.zeros(M, np.int64)
+    dk = np.zeros(M, np.uint32)
+    for c in range(cams.n):
+        r, n_, d = binning.binning_fp32(scene.means, scene.scales, scene.quats, cams.viewmat[c],
+                                        cams.intrin[c], cams.width[c], cams.height[c], ocfg)
+        sl = slice(c * N, (c + 1) * N)
+        rect[sl], nt[sl], dk[sl] = r, n_, d
+    vis = nt > 0
+    np.testing.assert_array_equal(g_nt, nt)
+    np.testing.assert_array_equal(g_dk[vis], dk[vis])
+    np.testing.assert_array_equal(g_rect[vis].astype(np.int64), rect[vis])
+    assert rast.n_isect() == int(nt.sum())
+    say(f"  binning equal on {M} pairs; n_isect {int(nt.sum())}")
+    # the depth presort is the permutation sorted by (depth key, pair id)
+    order = rast.view("order", torch.int32, M).cpu().numpy().view(np.uint32).astype(np.int64)
+    key = g_dk[order].astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(M))
+    assert np.all((np.diff(key) > 0) | ((np.diff(key) == 0) & (np.diff(order) > 0)))
+    del g_rect, g_dk, order, key
+
+    # -- sampled tiles ---------------------------------------------------------
+    base, rng_all = rast.lists()
+    vals = rast.view("vals", torch.int32, int(base[-1])).cpu().numpy().view(np.uint32)
+    image = rast.image.cpu().numpy().astype(np.float64)
+    final_T = rast.final_T.cpu().numpy().astype(np.float64)
+    last = rast.last.cpu().numpy().astype(np.int64)
+    contrib = rast.view("tile_contrib", torch.int32, T).cpu().numpy().astype(np.int64)
+    proj = rast.view("proj", torch.uint8, 64 * M).cpu().numpy()
+    rec = proj.view(np.float64).reshape(M, 8)
+    recf = proj.view(np.float32).reshape(M, 16)
+    rs = np.random.default_rng(2024)
+    samples = []
+    for c in VIEWS_SAMPLED:
+        t0, t1 = int(lay.tile_off[c]), int(lay.tile_off[c + 1])
+        busy = [t for t in range(t0, t1) if rng_all[0, t + 1] > rng_all[0, t]]
+        samples += [(c, int(t)) for t in rs.choice(busy, TILES_PER_VIEW, replace=False)]
+
+    G = np.zeros(image.size, np.float32)
+    G_full = scenes.upstream_grad(cams, 7040)
+    tiles = []
+    for c, gt in samples:
+        W, H = int(cams.width[c]), int(cams.height[c])
+        gx = lay.grid[c][0]
+        ty, tx = divmod(gt - int(lay.tile_off[c]), gx)
+        ref = binning.tile_list(rect, nt, dk.astype(np.uint32), gt, lay)
+        segs = [vals[base[k] + rng_all[k, gt]: base[k] + rng_all[k, gt + 1]]
+                for k in range(len(base) - 1)]
+        got = np.concatenate(segs).astype(np.int64)
+        assert len(got) <= len(ref)
+        np.testing.assert_array_equal(got, ref[:len(got)])
+        # the oracle's composite over its own (complete) list of the tile
+        ids = ref - c * N
+        sub = projection.project(scene.means[ids], scene.scales[ids], scene.quats[ids],
+                                 scene.sh[ids], 3, cams.viewmat[c], cams.intrin[c], W, H, ocfg)
+        px, py = composite._tile_pixels(tx, ty, W, H, ocfg)
+        opac = scene.opacity[ids].astype(np.float64)
+        res = composite.composite_tile(np.arange(len(ids)), px, py, sub["mean2d"], sub["conic"],
+                                       opac, sub["rgb"], ocfg, want_pairs=True)
+        # the library's list reaches every pixel's last contributor
+        assert len(got) >= res["last"].max()
+        # the projected records of the splats the composite used
+        u = ref[:res["last"].max()]
+        k = np.arange(len(u))
+        np.testing.assert_allclose(rec[u, 0:2], sub["mean2d"][k], rtol=1e-12, atol=1e-9)
+        scale = np.abs(sub["conic"][k]).max(axis=1, keepdims=True)
+        assert np.all(np.abs(rec[u, 2:5] - sub["conic"][k]) <= 1e-9 * scale)
+        np.testing.assert_allclose(recf[u, 10:13], sub["rgb"][k], rtol=1e-6, atol=1e-7)
+        pix = int(lay.pix_off[c]) + py * W + px
+        ok = ~res["flag"]
+        np.testing.assert_array_equal(last[pix][ok], res["last"][ok])
+        assert_close("final_T", final_T[pix], res["T"], mask=ok)
+        for ch in range(3):
+            ib = 3 * int(lay.pix_off[c]) + ch * W * H + py * W + px
+            assert_close(f"image[{ch}]", image[ib], res["C"][:, ch], mask=ok)
+            G[ib[ok]] = G_full[ib[ok]]
+        if not res["flag"].any():
+            want = 0 if res["pairs"] is None else len(res["pairs"]["p"])
+            assert contrib[gt] == want, (gt, contrib[gt], want)
+        tiles.append((c, gt, ids, sub, res, px, py, ok))
+    say(f"  {len(tiles)} sampled tiles equal")
+
+    # -- gradients ---------------------------------------------------------------
+    grads = rast.backward(sp, torch.from_numpy(G).cuda())
+    torch.cuda.synchronize()
+    got = {k: v.detach().cpu().numpy().astype(np.float64) for k, v in grads.items()}
+    want = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)),
+                opacity=np.zeros(N), sh=np.zeros((N, 16, 3)))
+    for c in VIEWS_SAMPLED:
+        W, H = int(cams.width[c]), int(cams.height[c])
+        mine = [t for t in tiles if t[0] == c]
+        ids = np.unique(np.concatenate([t[2] for t in mine]))
+        sub = projection.project(scene.means[ids], scene.scales[ids], scene.quats[ids],
+                                 scene.sh[ids], 3, cams.viewmat[c], cams.intrin[c], W, H, ocfg)
+        acc = [np.zeros((len(ids), 3)), np.zeros(len(ids)), np.zeros((len(ids), 3)),
+               np.zeros((len(ids), 2))]
+        for _, gt, tid, _, res, px, py, ok in mine:
+            loc = np.searchsorted(ids, tid)
+            r2 = dict(res)
+            if res["pairs"] is not None:
+                r2["pairs"] = dict(res["pairs"], id=loc[res["pairs"]["id"]])
+            Gt = np.stack([G[3 * int(lay.pix_off[c]) + ch * W * H + py * W + px]
+                           for ch in range(3)], axis=1).astype(np.float64)
+            r = composite.reverse_tile(r2, Gt, sub["mean2d"], sub["conic"],
+                                       scene.opacity[ids].astype(np.float64), sub["rgb"], ocfg,
+                                       len(ids))
+            for a, b in zip(acc, r):
+                a += b
+        gm, gs, gq, gsh = projection.project_backward(sub, scene.sh[ids], 3, acc[3], acc[2], acc[0])
+        want["means"][ids] += gm
+        want["scales"][ids] += gs
+        want["quats"][ids] += gq
+        want["opacity"][ids] += acc[1]
+        want["sh"][ids] += gsh
+    touched = np.zeros(N, bool)
+    for c in VIEWS_SAMPLED:
+        touched[np.unique(np.concatenate([t[2] for t in tiles if t[0] == c]))] = True
+    for k in ("means", "scales", "quats"):
+        assert np.all(got[k][:, ~touched] == 0.0), k
+        assert_close(f"d_{k}", got[k][:, touched].T, want[k][touched])
+    assert np.all(got["opacity"][~touched] == 0.0)
+    assert_close("d_opacity", got["opacity"][touched], want["opacity"][touched])
+    gsh_ = got["sh"].reshape(16, 3, N).transpose(2, 0, 1)
+    assert np.all(gsh_[~touched] == 0.0)
+    assert_close("d_sh", gsh_[touched], want["sh"][touched])

@@ -10,9 +10,9 @@ import pytest
 
 from oracle import render_backward, render_forward
 from paper_2411_12440_amd import scenes
-from tests.gpu_helpers import (assert_close, cfg_pair, compare_binning, compare_forward,
-                               compare_grads, compare_projection, gpu_arrays, gpu_forward,
-                               pixel_flags_to_image, say)
+from tests.gpu_helpers import (assert_close, cfg_pair, compare_binning, compare_contributions,
+                               compare_forward, compare_grads, compare_projection, gpu_arrays,
+                               gpu_forward, pixel_flags_to_image, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -44,10 +44,11 @@ def test_workload1_forward(chunks):
     ocfg, gkw = cfg_pair(depth_chunks=chunks)
     rast, _ = gpu_forward(scene, off, cams, gkw)
     g = gpu_arrays(rast)
-    fw = render_forward(scene, off, cams, ocfg)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
     compare_binning(g, fw)
     compare_projection(g, fw)
     compare_forward(g, fw, cams)
+    compare_contributions(rast, fw)
 
 
 @pytest.mark.parametrize("tw,th,batch", [(16, 16, 0), (16, 8, 64), (8, 8, 0), (32, 8, 128)])
@@ -127,6 +128,34 @@ def test_workload2_binning_and_sampled_tiles(chunks):
     compare_forward(g, fw, cams)
     go = render_backward(fw, scene, cams, G)
     compare_grads(grads, go, scene)
+
+
+@pytest.mark.parametrize("chunks", [1, 4])
+def test_alpha_gradient_mean2d_norm_and_counts(chunks):
+    """The accumulated-opacity upstream gradient, the per-pair norm of the
+    projected-centre gradient and the per-tile contribution counts."""
+    import torch
+    say(f"case: dL/dalpha + mean2d_norm, 2500 splats SH2 176x112, depth chunks {chunks}")
+    scene = scenes.make_scene(2500, 61, -3.0, 0.5, 2)
+    cams = scenes.front_camera(176, 112)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair(ags=True, bg=(0.3, 0.1, 0.2), depth_chunks=chunks)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    keep = ~fw.flag
+    G = scenes.upstream_grad(cams, 7011) * pixel_flags_to_image(keep, cams)
+    GA = np.random.default_rng(7012).normal(size=fw.final_T.size).astype(np.float32) * keep
+    rast, sp = gpu_forward(scene, off, cams, gkw)
+    compare_contributions(rast, fw)
+    grads = rast.backward(sp, torch.from_numpy(G.astype(np.float32)).cuda(),
+                          dL_dalpha=torch.from_numpy(GA).cuda(), mean2d_norm=True)
+    torch.cuda.synchronize()
+    got = _grads_to_numpy(grads)
+    go = render_backward(fw, scene, cams, G, dL_dalpha=GA)
+    compare_grads(got, go, scene)
+    assert_close("mean2d_norm", got["mean2d_norm"], go["mean2d_norm"])
+    # the alpha term changes the result (it is not silently ignored)
+    g0 = render_backward(fw, scene, cams, G)
+    assert np.linalg.norm(go["opacity"] - g0["opacity"]) > 1e-3 * np.linalg.norm(g0["opacity"])
 
 
 def test_empty_and_culled():

@@ -501,6 +501,49 @@ def test_reverse_pass_against_finite_differences(seed, clip):
         assert _rms_close(g[name].reshape(-1), fd, 1e-5), name
 
 
+def test_alpha_channel_gradient_against_finite_differences():
+    """Loss = G . image + GA . (1 - T_final): the accumulated-opacity term of
+    the reverse pass against central differences of the forward pass."""
+    sc, cams, G = _tiny_grad_problem(3)
+    cfg = RasterConfig.strict()
+    rng = np.random.default_rng(77)
+    GA = rng.normal(size=int(cams.width[0]) * int(cams.height[0]))
+
+    def loss(scene):
+        fw = render_forward(scene, np.array([0, sc.n]), cams, cfg, want_pairs=True)
+        return float(np.dot(G.astype(np.float64), fw.image) + np.dot(GA, 1.0 - fw.final_T)), fw
+
+    _, fw = loss(sc)
+    g = render_backward(fw, sc, cams, G, dL_dalpha=GA)
+    g_img = render_backward(fw, sc, cams, G)
+    assert not np.allclose(g["opacity"], g_img["opacity"])     # the term is not empty
+    fields = dict(means=sc.means, scales=sc.scales, quats=sc.quats, opacity=sc.opacity, sh=sc.sh)
+    for name in ("means", "opacity", "scales"):
+        flat = fields[name].reshape(-1)
+        fd = np.zeros(flat.size)
+        for i in range(flat.size):
+            h = 1e-6 * max(1.0, abs(float(flat[i])))
+            vals = []
+            for sgn in (+1, -1):
+                pert = {k: v.astype(np.float64).copy() for k, v in fields.items()}
+                pert[name].reshape(-1)[i] += sgn * h
+                sc2 = scenes.Scene(pert["means"], pert["scales"], pert["quats"], pert["opacity"],
+                                   pert["sh"], sc.sh_degree)
+                vals.append(loss(sc2)[0])
+            fd[i] = (vals[0] - vals[1]) / (2 * h)
+        assert _rms_close(g[name].reshape(-1), fd, 1e-5), name
+
+
+def test_mean2d_norm_is_the_norm_of_the_projected_centre_gradient():
+    sc, cams, G = _tiny_grad_problem(4)
+    cfg = RasterConfig.strict()
+    fw = render_forward(sc, np.array([0, sc.n]), cams, cfg, want_pairs=True)
+    g = render_backward(fw, sc, cams, G)
+    gm = g["pair"]["mean2d"]
+    np.testing.assert_allclose(g["mean2d_norm"], np.hypot(gm[:, 0], gm[:, 1]), rtol=1e-15)
+    assert np.count_nonzero(g["mean2d_norm"]) >= 3
+
+
 @pytest.mark.parametrize("ags", [False, True])
 @pytest.mark.parametrize("deg", [0, 3])
 def test_reverse_pass_against_autograd(ags, deg):
