@@ -8,14 +8,16 @@ sphere of radius 4 around the scene.  One step is the whole path over all
 ranges), forward compositing, backward compositing and projection backward,
 with a seeded N(0, 1) upstream image gradient.
 
-Two paths are timed with the same kernels:
-  batched   all 8 views in one call sequence (one workspace, no host sync)
+Paths timed with the same kernels:
+  batched   all 8 views in one call sequence (one workspace, no host sync),
+            captured once in a HIP graph and replayed: the headline value
+  eager     the batched sequence launched call by call with a HIP event pair
+            around every kernel on its stream: per-kernel durations
   per-view  one view at a time, each with its own right-sized workspace and
             a host read-back of the intersection count after binning
-The headline value is the batched rate.  The JSON line also carries the
-per-view rate, the dominant kernel's roofline fraction (kernel durations from
-HIP events recorded around every library launch during the timed region) and
-the FP64 oracle timed on a bounded sample on the host CPU.
+The JSON line also carries the per-view rate, the dominant kernel's roofline
+fraction (its algorithmic work over its average event-timed duration) and the
+FP64 oracle timed on a bounded sample on the host CPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -194,7 +196,7 @@ def main():
     import torch
 
     from paper_2411_12440_amd import binding as B
-    from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
+    from paper_2411_12440_amd.rasterizer import Rasterizer, StepGraph, scene_to_device
     from paper_2411_12440_amd import scenes as S
 
     dev = torch.device("cuda:0")
@@ -222,21 +224,36 @@ def main():
         rast.rasterize_fwd()
         rast.rasterize_bwd(sp, G_all, grads)
 
+    # headline: the whole step captured once in a HIP graph, replayed
+    log("bench: capturing the batched step in a HIP graph")
+    graph = StepGraph(rast, sp, G_all, grads)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} graph replays (n_isect={n_isect})")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / args.steps
+    assert not rast.overflowed()
+    # the same kernels launched eagerly, each bracketed by HIP events on its
+    # stream, for per-kernel durations
     for _ in range(args.warmup):
         step_batched()
     torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} batched steps (n_isect={n_isect})")
+    log(f"bench: timing {args.steps} eager batched steps with kernel events")
     B.ls_profile_read(reset=True)
     B.ls_profile_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record()
     for _ in range(args.steps):
         step_batched()
     e1.record()
     torch.cuda.synchronize()
     B.ls_profile_enable(False)
-    ms_batched = e0.elapsed_time(e1) / args.steps
+    ms_eager = e0.elapsed_time(e1) / args.steps
     ktimes = B.ls_profile_read(reset=True)
     assert not rast.overflowed()
     last = rast.last.to(torch.int64)
@@ -346,6 +363,9 @@ def main():
                    "pairs_to_last": Q, "contributing_pairs": Qc, "ags": bool(args.ags),
                    "tile": "16x16",
                    "parallelism": "single GPU"},
+        "eager": {"ms_per_step": round(ms_eager, 4),
+                  "value": round(P / (ms_eager * 1e-3) / 1e6, 3),
+                  "note": "same step launched eagerly with an event pair around every kernel"},
         "per_view": per_view,
         "roofline": roof,
         "kernels": kernels[:12],

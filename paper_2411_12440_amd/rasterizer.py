@@ -146,6 +146,42 @@ class Rasterizer:
         return int(self.view("tile_contrib", torch.int32, T).to(torch.int64).sum().item())
 
 
+class StepGraph:
+    """One full pass over every camera (project -> bin_sort -> rasterize_fwd
+    -> rasterize_bwd) captured once into a HIP graph and replayed.
+
+    The graph holds the addresses of the splat tensors, the upstream
+    gradient(s), the gradient outputs and the rasterizer's workspace: update
+    inputs in place (``copy_``) between replays.  Nothing in the captured
+    sequence synchronises with the host, so a replay whose lists outgrow the
+    workspace only raises the overflow flag: check ``rast.overflowed()`` when
+    the scene changes, and capture again after growing the workspace.
+    """
+
+    def __init__(self, rast: Rasterizer, sp, dL_dimage, grads, dL_dalpha=None):
+        self.rast, self.sp, self.dL_dimage, self.grads = rast, sp, dL_dimage, grads
+        self.dL_dalpha = dL_dalpha
+        dev = rast.device
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):            # one eager pass off the capture stream
+            self._step()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step()
+
+    def _step(self):
+        r = self.rast
+        r.project(self.sp)
+        r.bin_sort()
+        r.rasterize_fwd()
+        r.rasterize_bwd(self.sp, self.dL_dimage, self.grads, dL_dalpha=self.dL_dalpha)
+
+    def replay(self):
+        self.graph.replay()
+
+
 class RenderFunction(torch.autograd.Function):
     """image = render(means, scales, quats, opacity, sh) through a Rasterizer;
     the backward pass is the library's hand-written reverse pass."""
