@@ -1,15 +1,22 @@
-"""Parity at the benchmark's full size and launch configuration: 3.2M splats
-with SH degree 3, eight 1920x1080 views on a sphere, AGS on, 16x16 tiles,
-seven depth chunks.  The FP64 oracle cannot composite all 16.6M pixels, so
-the test checks
+"""Parity at full workload sizes, in the launch configuration the benchmark
+times (AGS on, 16x16 tiles, seven depth chunks):
+
+  * workload 40: 3.2M splats with SH degree 3, eight 1920x1080 views on a
+    sphere (the benchmark itself);
+  * workload 3: 1M splats, 16 cameras of uneven resolution;
+  * workload 5: 4 scenes (200k to 2M splats), 64 cameras of mixed
+    resolution, 16 per scene.
+
+The FP64 oracle cannot composite every pixel at these sizes, so each test
+checks
 
   * the FP32 binning integers (rect, tiles touched, depth key) of every pair
     of every view bit for bit, and the depth order and intersection count by
     their definitions;
   * a seeded sample of tiles one by one: each tile's list (a prefix of its
-    plain-definition list that reaches the tile's last contributor), the
-    projected records of its splats, the composite (image, final_T, last) and
-    the contribution count;
+    plain-definition list that reaches every pixel's last contributor), the
+    projected records the composite reads, the composite (image, final_T,
+    last) and the tile's contribution count;
   * the gradients of every splat for an upstream gradient that is non-zero on
     the sampled tiles only (every other splat must receive exactly zero).
 """
@@ -25,9 +32,6 @@ from tests.gpu_helpers import assert_close, cfg_pair, say
 
 pytestmark = pytest.mark.gpu
 
-VIEWS_SAMPLED = (0, 5)
-TILES_PER_VIEW = 6
-
 
 @pytest.fixture(scope="module", autouse=True)
 def _need_gpu():
@@ -36,23 +40,23 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def test_benchmark_configuration_sampled():
+def _sampled_parity(k, views, tiles_per_view, seed):
     import torch
     from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
 
-    say("case: full size, 3.2M splats SH3, 8 x 1920x1080, AGS, depth chunks 7")
-    scene, off, cams = scenes.workload(40)
+    scene, off, cams = scenes.workload(k)
     N = scene.n
+    deg = scene.sh_degree
     ocfg, gkw = cfg_pair(ags=True, depth_chunks=7)
     sp = scene_to_device(scene)
-    rast = Rasterizer(cams, off, capacity=1 << 24, sh_degree=3, **gkw)
+    rast = Rasterizer(cams, off, capacity=1 << 24, sh_degree=deg, **gkw)
     rast.forward(sp)
     torch.cuda.synchronize()
     assert not rast.overflowed()
     L = rast.layout
     M, T = int(L.n_pairs), int(L.n_tiles)
     lay = layout(off, cams, ocfg)
-    assert M == cams.n * N and T == int(lay.tile_off[-1])
+    assert M == int(lay.pair_off[-1]) and T == int(lay.tile_off[-1])
 
     # -- binning integers of every pair, bit for bit -------------------------
     g_rect = rast.view("rect", torch.int16, 4 * M).cpu().numpy().view(np.uint16).reshape(M, 4)
@@ -62,17 +66,18 @@ def test_benchmark_configuration_sampled():
     nt = np.zeros(M, np.int64)
     dk = np.zeros(M, np.uint32)
     for c in range(cams.n):
-        r, n_, d = binning.binning_fp32(scene.means, scene.scales, scene.quats, cams.viewmat[c],
-                                        cams.intrin[c], cams.width[c], cams.height[c], ocfg)
-        sl = slice(c * N, (c + 1) * N)
-        rect[sl], nt[sl], dk[sl] = r, n_, d
+        s = slice(int(lay.splat_lo[c]), int(lay.splat_hi[c]))
+        r, n_, d = binning.binning_fp32(scene.means[s], scene.scales[s], scene.quats[s],
+                                        cams.viewmat[c], cams.intrin[c], cams.width[c],
+                                        cams.height[c], ocfg)
+        m = slice(int(lay.pair_off[c]), int(lay.pair_off[c + 1]))
+        rect[m], nt[m], dk[m] = r, n_, d
     vis = nt > 0
     np.testing.assert_array_equal(g_nt, nt)
     np.testing.assert_array_equal(g_dk[vis], dk[vis])
     np.testing.assert_array_equal(g_rect[vis].astype(np.int64), rect[vis])
     assert rast.n_isect() == int(nt.sum())
     say(f"  binning equal on {M} pairs; n_isect {int(nt.sum())}")
-    # the depth presort is the permutation sorted by (depth key, pair id)
     order = rast.view("order", torch.int32, M).cpu().numpy().view(np.uint32).astype(np.int64)
     key = g_dk[order].astype(np.int64)
     assert np.array_equal(np.sort(order), np.arange(M))
@@ -89,30 +94,31 @@ def test_benchmark_configuration_sampled():
     proj = rast.view("proj", torch.uint8, 64 * M).cpu().numpy()
     rec = proj.view(np.float64).reshape(M, 8)
     recf = proj.view(np.float32).reshape(M, 16)
-    rs = np.random.default_rng(2024)
+    rs = np.random.default_rng(seed)
     samples = []
-    for c in VIEWS_SAMPLED:
+    for c in views:
         t0, t1 = int(lay.tile_off[c]), int(lay.tile_off[c + 1])
-        busy = [t for t in range(t0, t1) if rng_all[0, t + 1] > rng_all[0, t]]
-        samples += [(c, int(t)) for t in rs.choice(busy, TILES_PER_VIEW, replace=False)]
+        per_tile = (rng_all[:, t0 + 1:t1 + 1] - rng_all[:, t0:t1]).sum(axis=0)
+        busy = t0 + np.nonzero(per_tile > 0)[0]
+        samples += [(c, int(t)) for t in rs.choice(busy, tiles_per_view, replace=False)]
 
     G = np.zeros(image.size, np.float32)
-    G_full = scenes.upstream_grad(cams, 7040)
+    G_full = scenes.upstream_grad(cams, 7000 + seed)
     tiles = []
     for c, gt in samples:
         W, H = int(cams.width[c]), int(cams.height[c])
         gx = lay.grid[c][0]
         ty, tx = divmod(gt - int(lay.tile_off[c]), gx)
-        ref = binning.tile_list(rect, nt, dk.astype(np.uint32), gt, lay)
-        segs = [vals[base[k] + rng_all[k, gt]: base[k] + rng_all[k, gt + 1]]
-                for k in range(len(base) - 1)]
+        ref = binning.tile_list(rect, nt, dk, gt, lay)
+        segs = [vals[base[q] + rng_all[q, gt]: base[q] + rng_all[q, gt + 1]]
+                for q in range(len(base) - 1)]
         got = np.concatenate(segs).astype(np.int64)
         assert len(got) <= len(ref)
         np.testing.assert_array_equal(got, ref[:len(got)])
         # the oracle's composite over its own (complete) list of the tile
-        ids = ref - c * N
+        ids = int(lay.splat_lo[c]) + (ref - int(lay.pair_off[c]))
         sub = projection.project(scene.means[ids], scene.scales[ids], scene.quats[ids],
-                                 scene.sh[ids], 3, cams.viewmat[c], cams.intrin[c], W, H, ocfg)
+                                 scene.sh[ids], deg, cams.viewmat[c], cams.intrin[c], W, H, ocfg)
         px, py = composite._tile_pixels(tx, ty, W, H, ocfg)
         opac = scene.opacity[ids].astype(np.float64)
         res = composite.composite_tile(np.arange(len(ids)), px, py, sub["mean2d"], sub["conic"],
@@ -121,11 +127,11 @@ def test_benchmark_configuration_sampled():
         assert len(got) >= res["last"].max()
         # the projected records of the splats the composite used
         u = ref[:res["last"].max()]
-        k = np.arange(len(u))
-        np.testing.assert_allclose(rec[u, 0:2], sub["mean2d"][k], rtol=1e-12, atol=1e-9)
-        scale = np.abs(sub["conic"][k]).max(axis=1, keepdims=True)
-        assert np.all(np.abs(rec[u, 2:5] - sub["conic"][k]) <= 1e-9 * scale)
-        np.testing.assert_allclose(recf[u, 10:13], sub["rgb"][k], rtol=1e-6, atol=1e-7)
+        q = np.arange(len(u))
+        np.testing.assert_allclose(rec[u, 0:2], sub["mean2d"][q], rtol=1e-12, atol=1e-9)
+        scale = np.abs(sub["conic"][q]).max(axis=1, keepdims=True)
+        assert np.all(np.abs(rec[u, 2:5] - sub["conic"][q]) <= 1e-9 * scale)
+        np.testing.assert_allclose(recf[u, 10:13], sub["rgb"][q], rtol=1e-6, atol=1e-7)
         pix = int(lay.pix_off[c]) + py * W + px
         ok = ~res["flag"]
         np.testing.assert_array_equal(last[pix][ok], res["last"][ok])
@@ -137,24 +143,27 @@ def test_benchmark_configuration_sampled():
         if not res["flag"].any():
             want = 0 if res["pairs"] is None else len(res["pairs"]["p"])
             assert contrib[gt] == want, (gt, contrib[gt], want)
-        tiles.append((c, gt, ids, sub, res, px, py, ok))
+        tiles.append((c, gt, ids, res, px, py))
     say(f"  {len(tiles)} sampled tiles equal")
 
     # -- gradients ---------------------------------------------------------------
     grads = rast.backward(sp, torch.from_numpy(G).cuda())
     torch.cuda.synchronize()
     got = {k: v.detach().cpu().numpy().astype(np.float64) for k, v in grads.items()}
+    K = scene.sh.shape[1]
     want = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)),
-                opacity=np.zeros(N), sh=np.zeros((N, 16, 3)))
-    for c in VIEWS_SAMPLED:
+                opacity=np.zeros(N), sh=np.zeros((N, K, 3)))
+    touched = np.zeros(N, bool)
+    for c in views:
         W, H = int(cams.width[c]), int(cams.height[c])
         mine = [t for t in tiles if t[0] == c]
         ids = np.unique(np.concatenate([t[2] for t in mine]))
+        touched[ids] = True
         sub = projection.project(scene.means[ids], scene.scales[ids], scene.quats[ids],
-                                 scene.sh[ids], 3, cams.viewmat[c], cams.intrin[c], W, H, ocfg)
+                                 scene.sh[ids], deg, cams.viewmat[c], cams.intrin[c], W, H, ocfg)
         acc = [np.zeros((len(ids), 3)), np.zeros(len(ids)), np.zeros((len(ids), 3)),
                np.zeros((len(ids), 2))]
-        for _, gt, tid, _, res, px, py, ok in mine:
+        for _, gt, tid, res, px, py in mine:
             loc = np.searchsorted(ids, tid)
             r2 = dict(res)
             if res["pairs"] is not None:
@@ -166,20 +175,33 @@ def test_benchmark_configuration_sampled():
                                        len(ids))
             for a, b in zip(acc, r):
                 a += b
-        gm, gs, gq, gsh = projection.project_backward(sub, scene.sh[ids], 3, acc[3], acc[2], acc[0])
+        gm, gs, gq, gsh = projection.project_backward(sub, scene.sh[ids], deg, acc[3], acc[2],
+                                                      acc[0])
         want["means"][ids] += gm
         want["scales"][ids] += gs
         want["quats"][ids] += gq
         want["opacity"][ids] += acc[1]
         want["sh"][ids] += gsh
-    touched = np.zeros(N, bool)
-    for c in VIEWS_SAMPLED:
-        touched[np.unique(np.concatenate([t[2] for t in tiles if t[0] == c]))] = True
     for k in ("means", "scales", "quats"):
         assert np.all(got[k][:, ~touched] == 0.0), k
         assert_close(f"d_{k}", got[k][:, touched].T, want[k][touched])
     assert np.all(got["opacity"][~touched] == 0.0)
     assert_close("d_opacity", got["opacity"][touched], want["opacity"][touched])
-    gsh_ = got["sh"].reshape(16, 3, N).transpose(2, 0, 1)
+    gsh_ = got["sh"].reshape(K, 3, N).transpose(2, 0, 1)
     assert np.all(gsh_[~touched] == 0.0)
     assert_close("d_sh", gsh_[touched], want["sh"][touched])
+
+
+def test_benchmark_configuration_sampled():
+    say("case: workload 40 (3.2M splats SH3, 8 x 1920x1080), AGS, depth chunks 7")
+    _sampled_parity(40, views=(0, 5), tiles_per_view=6, seed=40)
+
+
+def test_uneven_cameras_sampled():
+    say("case: workload 3 (1M splats SH3, 16 uneven cameras), AGS, depth chunks 7")
+    _sampled_parity(3, views=(2, 11), tiles_per_view=4, seed=3)
+
+
+def test_multi_scene_64_cameras_sampled():
+    say("case: workload 5 (4 scenes, 3.7M splats, 64 cameras), AGS, depth chunks 7")
+    _sampled_parity(5, views=(1, 22, 40, 63), tiles_per_view=2, seed=5)
