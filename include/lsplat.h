@@ -188,7 +188,10 @@ typedef struct ls_cameras {
  *   flags      int32[16]: flags[0] != 0 when the entries did not fit in the
  *              capacity (the composite is then incomplete: grow the capacity
  *              to at least n_isect and run again).
- *   grad2d     [9][M] float: per-pair 2D gradient sums (backward), field-major.
+ *   grad2d     [9][M] double: per-pair sums over the pair's pixels (backward),
+ *              field-major: dL/d(projected centre) x, y; dL/da, dL/db, dL/dc
+ *              for the dilated 2D covariance [[a, b], [b, c]] (b a single
+ *              parameter); dL/dopacity; dL/drgb (3).
  *   tile_contrib [T] uint32: per tile, the (pixel, splat) pairs that
  *              contributed to the composite in the last ls_rasterize_fwd call
  *              (alpha >= alpha_min, before the pixel stopped); the backward

@@ -98,6 +98,23 @@ def project(means, scales, quats, sh, sh_degree, viewmat, intrin, width, height,
                 fx=fx, fy=fy, scales=s)
 
 
+def cov2d_grad(conic, g_conic):
+    """Gradient w.r.t. the 2D covariance (a, b, c of [[a, b], [b, c]], b one
+    parameter) from the gradient w.r.t. the conic (A, B, C) = its inverse:
+    for a symmetric matrix and its inverse, dL/dcov = -conic (dL/dconic) conic,
+    with the off-diagonal gradient split over both slots."""
+    n = len(conic)
+    A, B, C = conic[:, 0], conic[:, 1], conic[:, 2]
+    conm = np.empty((n, 2, 2))
+    conm[:, 0, 0], conm[:, 0, 1], conm[:, 1, 0], conm[:, 1, 1] = A, B, B, C
+    gcm = np.empty((n, 2, 2))
+    gcm[:, 0, 0] = g_conic[:, 0]
+    gcm[:, 0, 1] = gcm[:, 1, 0] = 0.5 * g_conic[:, 1]
+    gcm[:, 1, 1] = g_conic[:, 2]
+    gcov = -conm @ gcm @ conm
+    return np.stack([gcov[:, 0, 0], 2.0 * gcov[:, 0, 1], gcov[:, 1, 1]], axis=1)
+
+
 def project_backward(p, sh, sh_degree, g_mean2d, g_conic, g_rgb):
     """Chain rule from per-pair 2D gradients to splat parameters.
 
@@ -105,17 +122,18 @@ def project_backward(p, sh, sh_degree, g_mean2d, g_conic, g_rgb):
     2 B dx dy + C dy^2; g_rgb [N,3].  Returns (g_means [N,3], g_scales [N,3],
     g_quats [N,4], g_sh [N,K,3]).  Opacity passes straight through.
     """
+    return project_backward_cov(p, sh, sh_degree, g_mean2d, cov2d_grad(p["conic"], g_conic),
+                                g_rgb)
+
+
+def project_backward_cov(p, sh, sh_degree, g_mean2d, gc, g_rgb):
+    """project_backward with the 2D shape gradient given w.r.t. the dilated
+    covariance (a, b, c of [[a, b], [b, c]], b one parameter)."""
     n = len(p["t"])
-    A, B, C = p["conic"][:, 0], p["conic"][:, 1], p["conic"][:, 2]
-    conm = np.empty((n, 2, 2))
-    conm[:, 0, 0], conm[:, 0, 1], conm[:, 1, 0], conm[:, 1, 1] = A, B, B, C
-    # gradient w.r.t. the full symmetric conic matrix (B sits in two entries)
-    gcm = np.empty((n, 2, 2))
-    gcm[:, 0, 0] = g_conic[:, 0]
-    gcm[:, 0, 1] = gcm[:, 1, 0] = 0.5 * g_conic[:, 1]
-    gcm[:, 1, 1] = g_conic[:, 2]
-    # conic = cov2d^-1  =>  dL/dcov2d = -conic (dL/dconic) conic
-    gcov = -conm @ gcm @ conm
+    gcov = np.empty((n, 2, 2))
+    gcov[:, 0, 0] = gc[:, 0]
+    gcov[:, 0, 1] = gcov[:, 1, 0] = 0.5 * gc[:, 1]
+    gcov[:, 1, 1] = gc[:, 2]
     T, Sigma, Wr = p["T"], p["Sigma"], p["Wr"]
     g_T = 2.0 * gcov @ T @ Sigma
     g_Sigma = np.swapaxes(T, 1, 2) @ gcov @ T

@@ -131,7 +131,7 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   L.chunk_base = take(8 * (K + 1));
   L.chunk_n = take(8 * K);
   L.flags = take(64);
-  L.grad2d = take(4 * kGrad2d * M);
+  L.grad2d = take(8 * kGrad2d * M);
   L.tile_contrib = take(4 * T);
   L.scratch = off;
   p->pre_keys_a = take(4 * M);
@@ -156,11 +156,13 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   // only holds the entries actually built, so the table is sized for
   // kSpanCover times the capacity (2 bytes per covered intersection).
   // complete lists: owner pair of every key-generation span
-  p->n_spans = p->K == 1 ? (std::max<int64_t>(cap, 1) + kKeygenSpan - 1) / kKeygenSpan + 2 : 1;
+  const int64_t span = p->K == 1 ? kKeygenSpan : kChunkSpan;
+  p->n_spans = (std::max<int64_t>(cap, 1) + span - 1) / span + 2;
   p->span_owner = take(4 * (size_t)p->n_spans);
   // depth chunks: per-pair alive counts and offsets, tile summed-area table
   p->span_cnt = take(4 * (p->K > 1 ? M : 1));
   p->span_off = take(4 * (p->K > 1 ? M : 1));
+  p->pmask = take(4 * (p->K > 1 ? M : 1));
   p->chunk_spans = take(8 * K);
   p->alive = take(4 * T);
   p->sat = take(4 * T);

@@ -178,7 +178,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
 #pragma unroll
     for (int w = 0; w < 4; ++w) s_wcnt[w][tid] = 0;
     __syncthreads();
-    uint32_t k[kSortItems], v[kSortItems], r[kSortItems];
+    uint32_t k[kSortItems], v[kSortItems], r[kSortItems], lead[kSortItems], base[kSortItems];
+    // Rank every key among the wave's keys of the same digit: ballot matching
+    // finds the lanes that share the digit; the lowest of them (the leader)
+    // adds the group's size to the wave's running count of that digit with
+    // an LDS atomic that returns the count before the add.  The 16 atomics
+    // do not wait for each other (one wave's LDS operations complete in
+    // order), and the leaders' results are broadcast afterwards.
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       const int idx = wave * (64 * kSortItems) + j * 64 + lane;
@@ -198,13 +204,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
       // lanes below this one with the same digit
       const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      uint32_t base = 0;
-      if (valid) base = s_wcnt[wave][d];
-      if (valid && pre == 0) s_wcnt[wave][d] = base + (uint32_t)__popcll(m);
+      base[j] = 0;
+      if (valid && pre == 0) base[j] = atomicAdd(&s_wcnt[wave][d], (uint32_t)__popcll(m));
+      lead[j] = m ? (uint32_t)__builtin_ctzll(m) : 0u;
       k[j] = key;
       v[j] = val;
-      r[j] = base + pre;
+      r[j] = pre;
     }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) r[j] += (uint32_t)__shfl((int)base[j], (int)lead[j], 64);
     __syncthreads();
     // per digit: wave prefix and tile-local start
     const uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
@@ -339,9 +347,28 @@ struct PairOffsets {
   }
 };
 
-struct SpanOffsets {
+// chunk mode: each pair's offset inside the chunk, and for every span of
+// kChunkSpan output entries the (chunk-local) pair that owns its first entry;
+// the pair owning the chunk's last entry is also recorded one span further,
+// so span s always finds its pairs between owner[s] and owner[s + 1]
+struct ChunkOffsets {
   uint32_t* off;
-  __device__ void operator()(int64_t s, int64_t base, int64_t) const { off[s] = (uint32_t)base; }
+  uint32_t* owner;
+  int64_t n_spans;
+  const int64_t* total;
+  __device__ void operator()(int64_t q, int64_t base, int64_t v) const {
+    off[q] = (uint32_t)base;
+    if (v > 0) {
+      for (int64_t sp = (base + kChunkSpan - 1) / kChunkSpan; sp * kChunkSpan < base + v && sp < n_spans;
+           ++sp)
+        owner[sp] = (uint32_t)q;
+      const int64_t n_total = *total;
+      if (base + v == n_total) {
+        const int64_t term = (n_total + kChunkSpan - 1) / kChunkSpan;
+        if (term < n_spans) owner[term] = (uint32_t)q;
+      }
+    }
+  }
 };
 
 template <class In, class Out>
@@ -579,38 +606,181 @@ __device__ __forceinline__ uint32_t sat_query(const uint32_t* S, int GX, int x0,
 }
 
 // Chunk c of the depth order (pair positions [lo, hi)): for each pair the
-// number of alive tiles in its rectangle.
+// number of alive tiles in its rectangle, and a mask that tells the writer
+// where they are: for a rectangle of at most kSmallRect tiles, bit j is tile j
+// (row-major) of the rectangle; a larger one gets all ones when every tile is
+// alive and 0 otherwise (then a wave of the second write kernel scans it).
+constexpr int kSmallRect = 32;
+
 __global__ __launch_bounds__(256) void chunk_count_kernel(
     const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
     const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
-    const uint32_t* __restrict__ sat, const int32_t* __restrict__ flags,
-    uint32_t* __restrict__ pcnt) {
+    const uint32_t* __restrict__ sat, const uint32_t* __restrict__ alive,
+    const int32_t* __restrict__ flags, uint32_t* __restrict__ pcnt,
+    uint32_t* __restrict__ pmask) {
   const int64_t p = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= hi) return;
-  uint32_t k = 0;
+  uint32_t k = 0, mask = 0;
   const ushort4 r = drect[p];
-  if (flags[0] == 0 && rect_tiles(r) != 0) {
+  const uint32_t area = rect_tiles(r);
+  if (flags[0] == 0 && area != 0) {
     uint32_t m = order[p];
     if (m >= (uint64_t)M) m = 0;
     const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
-    k = sat_query(sat + ci.tile_off, ci.GX, r.x, r.y, r.z, r.w);
+    if (area <= (uint32_t)kSmallRect) {
+      int j = 0;
+      for (int ty = r.y; ty <= r.w; ++ty) {
+        const uint32_t* row = alive + ci.tile_off + (int64_t)ty * ci.GX;
+        for (int tx = r.x; tx <= r.z; ++tx, ++j)
+          if (row[tx]) mask |= 1u << j;
+      }
+      k = (uint32_t)__popc(mask);
+    } else {
+      k = sat_query(sat + ci.tile_off, ci.GX, r.x, r.y, r.z, r.w);
+      mask = (k == area) ? 0xFFFFFFFFu : 0u;
+    }
   }
   pcnt[p - lo] = k;
+  pmask[p - lo] = mask;
 }
 
-// Write the chunk's entries: each pair its alive tiles, row-major, at the
-// scanned offset; pairs follow the depth order, so the chunk's entries are in
-// the same relative order as in the complete lists.  A pair whose rectangle
-// is small is written by its own thread; larger ones are queued in LDS and
-// written by a whole wave, 64 tiles per step, with ballot compaction, so a
-// screen-sized splat neither serialises a wave nor scatters its stores.
-constexpr int kSmallRect = 32;
+// position of the k-th (from 0) set bit of x; requires k < popcount(x)
+__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k) {
+  uint32_t pos = 0, c;
+  c = (uint32_t)__popc(x & 0xFFFFu);
+  if (k >= c) { k -= c; x >>= 16; pos += 16; }
+  c = (uint32_t)__popc(x & 0xFFu);
+  if (k >= c) { k -= c; x >>= 8; pos += 8; }
+  c = (uint32_t)__popc(x & 0xFu);
+  if (k >= c) { k -= c; x >>= 4; pos += 4; }
+  c = (uint32_t)__popc(x & 0x3u);
+  if (k >= c) { k -= c; x >>= 2; pos += 2; }
+  c = x & 1u;
+  if (k >= c) pos += 1;
+  return pos;
+}
 
-__global__ __launch_bounds__(256) void chunk_write_kernel(
+// q / w for q < 2^24, w >= 1: a float estimate corrected to the exact quotient
+__device__ __forceinline__ uint32_t div_small(uint32_t q, uint32_t w, uint32_t* rem) {
+  uint32_t d = (uint32_t)((float)q * __builtin_amdgcn_rcpf((float)w));
+  int32_t r = (int32_t)q - (int32_t)(d * w);
+  while (r < 0) { --d; r += (int32_t)w; }
+  while (r >= (int32_t)w) { ++d; r -= (int32_t)w; }
+  *rem = (uint32_t)r;
+  return d;
+}
+
+// Write the chunk's entries at their scanned offsets, pairs in depth order, so
+// the chunk's entries keep the relative order of the complete lists.  Each
+// block iteration owns a span of kChunkSpan output entries: the span's owning
+// pairs are found between two entries of the span-owner table (skipping the
+// pairs with no alive tile), their start positions marked in LDS, and an LDS
+// max-scan gives every entry its pair; the entry's tile is its rank among the
+// pair's alive tiles (the mask), and consecutive threads write consecutive
+// entries.  Entries of a large, partly alive rectangle are left to
+// chunk_write_big_kernel.
+struct ChunkSpan {
+  uint32_t slot[kChunkSpan];
+  uint32_t off[kChunkSpan], mask[kChunkSpan], m[kChunkSpan], gbase[kChunkSpan], wgx[kChunkSpan];
+  int32_t wmax[4];
+};
+
+__device__ __forceinline__ void chunk_span_pair(ChunkSpan& t, int sl, int64_t q, int64_t lo,
+                                                const uint32_t* __restrict__ order,
+                                                const ushort4* __restrict__ drect,
+                                                const CamInfo* __restrict__ cams, int C, int64_t M,
+                                                const uint32_t* __restrict__ poff,
+                                                const uint32_t* __restrict__ pmask) {
+  uint32_t m = order[lo + q];
+  if (m >= (uint64_t)M) m = 0;
+  const ushort4 rc = drect[lo + q];
+  const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
+  t.off[sl] = poff[q];
+  t.mask[sl] = pmask[q];
+  t.m[sl] = m;
+  t.gbase[sl] = (uint32_t)(ci.tile_off + (int64_t)rc.y * ci.GX + rc.x);
+  t.wgx[sl] = (uint32_t)(rc.z - rc.x + 1) | ((uint32_t)ci.GX << 16);
+}
+
+__global__ __launch_bounds__(256) void chunk_write_span_kernel(
     const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
     const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
-    const uint32_t* __restrict__ sat, const uint32_t* __restrict__ alive,
     const uint32_t* __restrict__ pcnt, const uint32_t* __restrict__ poff,
+    const uint32_t* __restrict__ pmask, const uint32_t* __restrict__ owner, int64_t n_spans,
+    const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ ChunkSpan t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n = *chunk_n;
+  const int64_t base = *chunk_base;
+  const int64_t np = hi - lo;
+  for (int64_t s = blockIdx.x; s * kChunkSpan < n && s + 1 < n_spans; s += gridDim.x) {
+    const int64_t k0 = s * kChunkSpan;
+    const int cnt = (int)((n - k0) < kChunkSpan ? (n - k0) : kChunkSpan);
+    int64_t qa = owner[s], qb = owner[s + 1];
+    if (qa > np - 1) qa = np - 1;
+    if (qb > np - 1) qb = np - 1;
+    if (qb < qa) qb = qa;
+    for (int i = tid; i < kChunkSpan; i += 256) t.slot[i] = 0;
+    if (tid == 0) chunk_span_pair(t, 0, qa, lo, order, drect, cams, C, M, poff, pmask);
+    __syncthreads();
+    for (int64_t q = qa + 1 + tid; q <= qb; q += 256) {
+      if (pcnt[q] == 0) continue;
+      const int64_t o = (int64_t)poff[q];
+      if (o <= k0 || o >= k0 + kChunkSpan) continue;
+      const int sl = (int)(o - k0);
+      t.slot[sl] = (uint32_t)sl;
+      chunk_span_pair(t, sl, q, lo, order, drect, cams, C, M, poff, pmask);
+    }
+    __syncthreads();
+    // inclusive max-scan of the start marks: entry i's pair is at slot[i]
+    constexpr int kPer = kChunkSpan / 256;
+    uint32_t loc[kPer];
+    uint32_t mx = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t o = t.slot[tid * kPer + k];
+      mx = o > mx ? o : mx;
+      loc[k] = mx;
+    }
+    uint32_t x = mx;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x = y > x ? y : x;
+    }
+    if (lane == 63) t.wmax[wave] = (int32_t)x;
+    uint32_t ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = 0;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) ex = (uint32_t)t.wmax[w] > ex ? (uint32_t)t.wmax[w] : ex;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) t.slot[tid * kPer + k] = loc[k] > ex ? loc[k] : ex;
+    __syncthreads();
+    for (int i = tid; i < cnt; i += 256) {
+      const uint32_t sl = t.slot[i];
+      const uint32_t mask = t.mask[sl];
+      if (mask == 0u) continue;            // a large, partly alive rectangle
+      const uint32_t local = (uint32_t)(k0 + i - (int64_t)t.off[sl]);
+      const uint32_t pos = mask == 0xFFFFFFFFu ? local : select_bit(mask, local);
+      const uint32_t wgx = t.wgx[sl];
+      uint32_t tx;
+      const uint32_t ty = div_small(pos, wgx & 0xFFFFu, &tx);
+      keys[base + k0 + i] = t.gbase[sl] + ty * (wgx >> 16) + tx;
+      vals[base + k0 + i] = t.m[sl];
+    }
+    __syncthreads();
+  }
+}
+
+// The large, partly alive rectangles of the chunk: queued per block, each
+// written by one wave, 64 tiles of the rectangle (row-major) per step with
+// ballot compaction.
+__global__ __launch_bounds__(256) void chunk_write_big_kernel(
+    const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
+    const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
+    const uint32_t* __restrict__ alive, const uint32_t* __restrict__ pcnt,
+    const uint32_t* __restrict__ poff, const uint32_t* __restrict__ pmask,
     const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ int64_t s_big[256];
@@ -620,58 +790,38 @@ __global__ __launch_bounds__(256) void chunk_write_kernel(
   if (tid == 0) s_nbig = 0;
   __syncthreads();
   const int64_t p = lo + (int64_t)blockIdx.x * 256 + tid;
-  const int64_t base = *chunk_base;
-  if (p < hi) {
-    uint32_t k = pcnt[p - lo];
-    if (k > 0) {
-      const ushort4 r = drect[p];
-      const int area = (r.z - r.x + 1) * (r.w - r.y + 1);
-      if (area > kSmallRect) {
-        s_big[atomicAdd(&s_nbig, 1)] = p;
-      } else {
-        uint32_t m = order[p];
-        if (m >= (uint64_t)M) m = 0;
-        const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
-        int64_t dst = base + poff[p - lo];
-        for (int ty = r.y; ty <= r.w && k > 0; ++ty) {
-          const int64_t row = ci.tile_off + (int64_t)ty * ci.GX;
-          for (int tx = r.x; tx <= r.z; ++tx) {
-            if (alive[row + tx]) {
-              keys[dst] = (uint32_t)(row + tx);
-              vals[dst] = m;
-              ++dst;
-              --k;
-            }
-          }
-        }
-      }
-    }
-  }
+  if (p < hi && pcnt[p - lo] > 0 && pmask[p - lo] == 0u) s_big[atomicAdd(&s_nbig, 1)] = p;
   __syncthreads();
   const int nbig = s_nbig;
+  const int64_t base = *chunk_base;
   for (int b = wave; b < nbig; b += 4) {
     const int64_t q = s_big[b];
     uint32_t m = order[q];
     if (m >= (uint64_t)M) m = 0;
     const ushort4 r = drect[q];
     const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
-    const uint32_t* S = sat + ci.tile_off;
+    const uint32_t w = (uint32_t)(r.z - r.x + 1);
+    const uint32_t area = w * (uint32_t)(r.w - r.y + 1);
+    const int64_t row0 = ci.tile_off + (int64_t)r.y * ci.GX + r.x;
     int64_t dst = base + poff[q - lo];
-    for (int ty = r.y; ty <= r.w; ++ty) {
-      if (sat_query(S, ci.GX, r.x, ty, r.z, ty) == 0u) continue;
-      const int64_t row = ci.tile_off + (int64_t)ty * ci.GX;
-      for (int x0 = r.x; x0 <= r.z; x0 += 64) {
-        const int tx = x0 + lane;
-        const bool keep = tx <= r.z && alive[row + tx] != 0u;
-        const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
-        if (keep) {
-          const int64_t at = dst + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-          keys[at] = (uint32_t)(row + tx);
-          vals[at] = m;
-        }
-        dst += __popcll(bal);
+    for (uint32_t i0 = 0; i0 < area; i0 += 64) {
+      const uint32_t i = i0 + (uint32_t)lane;
+      bool keep = false;
+      uint32_t tile = 0;
+      if (i < area) {
+        uint32_t tx;
+        const uint32_t ty = div_small(i, w, &tx);
+        tile = (uint32_t)(row0 + (int64_t)ty * ci.GX + tx);
+        keep = alive[tile] != 0u;
       }
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
+      if (keep) {
+        const int64_t at = dst + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        keys[at] = tile;
+        vals[at] = m;
+      }
+      dst += __popcll(bal);
     }
   }
 }
@@ -873,6 +1023,8 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
     int32_t* flags = (int32_t*)(ws + p.lay.flags);
     uint32_t* pcnt = (uint32_t*)(ws + p.span_cnt);
     uint32_t* poff = (uint32_t*)(ws + p.span_off);
+    uint32_t* pmask = (uint32_t*)(ws + p.pmask);
+    uint32_t* owner = (uint32_t*)(ws + p.span_owner);
     const ushort4* drect = (const ushort4*)(ws + p.drect);
     uint32_t *k0, *v0;
     keygen_targets(p, ws, &k0, &v0);
@@ -882,26 +1034,31 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
       ProfScope ps("chunk_count", s);
       hipLaunchKernelGGL(alive_sat_kernel, dim3(p.C), dim3(256), 0, s, cams, alive, sat);
       hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams, p.C,
-                         M, lo, hi, sat, flags, pcnt);
+                         M, lo, hi, sat, alive, flags, pcnt, pmask);
     }
     {
       int64_t* part = (int64_t*)(ws + p.scan_part);
       const int B = scan_blocks_for(n);
       SpanCount in{pcnt};
-      SpanOffsets out{poff};
+      ChunkOffsets out{poff, owner, p.n_spans, part + B};
       ProfScope ps("chunk_scan", s);
       hipLaunchKernelGGL(scan_reduce<SpanCount>, dim3(B), dim3(kScanThreads), 0, s, in, nullptr, n,
                          B, part);
       hipLaunchKernelGGL(scan_parts, dim3(1), dim3(1024), 0, s, part, B);
-      hipLaunchKernelGGL((scan_down<SpanCount, SpanOffsets>), dim3(B), dim3(kScanThreads), 0, s,
+      hipLaunchKernelGGL((scan_down<SpanCount, ChunkOffsets>), dim3(B), dim3(kScanThreads), 0, s,
                          in, out, nullptr, n, B, part);
       hipLaunchKernelGGL(chunk_finalize, dim3(1), dim3(64), 0, s, part + B, chunk_base, chunk_n,
                          flags, p.cap);
     }
     {
       ProfScope ps("chunk_write", s);
-      hipLaunchKernelGGL(chunk_write_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams, p.C,
-                         M, lo, hi, sat, alive, pcnt, poff, chunk_base, chunk_n, k0, v0);
+      const int64_t spans = (p.cap + kChunkSpan - 1) / kChunkSpan;
+      const unsigned sgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(spans, 4096));
+      hipLaunchKernelGGL(chunk_write_span_kernel, dim3(sgrid), dim3(256), 0, s, order, drect, cams,
+                         p.C, M, lo, hi, pcnt, poff, pmask, owner, p.n_spans, chunk_base, chunk_n,
+                         k0, v0);
+      hipLaunchKernelGGL(chunk_write_big_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams,
+                         p.C, M, lo, hi, alive, pcnt, poff, pmask, chunk_base, chunk_n, k0, v0);
     }
     if ((e = hipGetLastError())) return e;
   } else {

@@ -61,7 +61,7 @@ struct Plan {
   // scratch sub-allocations (byte offsets from the workspace base)
   size_t sort_keys_b = 0, sort_vals_b = 0, pre_keys_a = 0, pre_keys_b = 0, pre_vals_a = 0, pre_vals_b = 0,
          hist = 0, digit_tot = 0, scan_part = 0, span_owner = 0, span_cnt = 0, span_off = 0,
-         chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, drect = 0;
+         chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, drect = 0, pmask = 0;
   int64_t n_spans = 0;        // entries of span_owner: ceil(cap / kKeygenSpan) + 1
   int32_t K = 1;              // depth chunks
   std::vector<int64_t> chunk_pos;   // [K + 1] pair positions in depth order
@@ -77,6 +77,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxSortBlocks = 1024;
 constexpr int kScanThreads = 256;
 constexpr int kKeygenSpan = 2048;   // output entries per key-generation block iteration
+constexpr int kChunkSpan = 1024;    // output entries per chunk-write block iteration
 constexpr int kMaxDepthChunks = 12;
 constexpr int kMaxScanBlocks = 1024;
 
@@ -129,6 +130,59 @@ __device__ __forceinline__ float wave_sum8(const float* v, int lane) {
   z += dpp_move<0x4E>(z);         // quad_perm [2,3,0,1]
   z += dpp_move<0xB1>(z);         // quad_perm [1,0,3,2]
   return z;
+}
+
+// FP64 versions: the same lane movements applied to both 32-bit halves.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_move_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double swap32_add_d(double a, double b) {
+  const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false,
+                                                   false);
+  const double a2 = __longlong_as_double(((long long)hi[0] << 32) | (long long)lo[0]);
+  const double b2 = __longlong_as_double(((long long)hi[1] << 32) | (long long)lo[1]);
+  return a2 + b2;
+}
+
+__device__ __forceinline__ double swap16_add_d(double a, double b) {
+  const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false,
+                                                   false);
+  const double a2 = __longlong_as_double(((long long)hi[0] << 32) | (long long)lo[0]);
+  const double b2 = __longlong_as_double(((long long)hi[1] << 32) | (long long)lo[1]);
+  return a2 + b2;
+}
+
+// wave_sum8 in FP64: lane 8g receives the sum of v[wave_sum8_field(g)].
+__device__ __forceinline__ double wave_sum8_d(const double* v, int lane) {
+  const double a = swap32_add_d(v[0], v[1]), b = swap32_add_d(v[2], v[3]);
+  const double c = swap32_add_d(v[4], v[5]), d = swap32_add_d(v[6], v[7]);
+  double x = swap16_add_d(a, b), y = swap16_add_d(c, d);
+  x += dpp_move_d<0x128>(x);        // row_ror:8
+  y += dpp_move_d<0x128>(y);
+  double z = (lane & 8) ? y : x;
+  z += dpp_move_d<0x141>(z);        // row_half_mirror
+  z += dpp_move_d<0x4E>(z);         // quad_perm [2,3,0,1]
+  z += dpp_move_d<0xB1>(z);         // quad_perm [1,0,3,2]
+  return z;
+}
+
+__device__ __forceinline__ double wave_sum_to_lane63_d(double x) {
+  x += dpp_move_d<0x128>(x);
+  x += dpp_move_d<0x124>(x);
+  x += dpp_move_d<0x122>(x);
+  x += dpp_move_d<0x121>(x);
+  x += dpp_move_d<0x142, 0xA>(x);
+  x += dpp_move_d<0x143, 0xC>(x);
+  return x;
 }
 
 __device__ __forceinline__ float wave_sum_to_lane63(float x) {

@@ -362,15 +362,16 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Backward.  grad2d[m][9] holds, per pair, the sums over its pixels of
-//   dL/dmean2d (x, y), dL/dA, dL/dB, dL/dC (conic entries, B counted once as
-//   a parameter of D'^2 = A dx^2 + 2B dx dy + C dy^2), dL/do, dL/drgb (3).
+// Backward.  grad2d[f][m] holds, per pair, the sums over its pixels of
+//   dL/dmean2d (x, y), dL/da, dL/db, dL/dc for the 2D covariance
+//   [[a, b], [b, c]] (b one parameter in both off-diagonal slots), dL/do,
+//   dL/drgb (3).
 // ---------------------------------------------------------------------------
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
     const CamInfo* __restrict__ cams, int C, int64_t N, const float* __restrict__ means,
     const float* __restrict__ scales, const float* __restrict__ quats,
-    const float* __restrict__ sh, float eps, float clip, const float* __restrict__ grad2d,
+    const float* __restrict__ sh, float eps, float clip, const double* __restrict__ grad2d,
     int64_t M, float* __restrict__ g_means, float* __restrict__ g_scales,
     float* __restrict__ g_quats, float* __restrict__ g_opac, float* __restrict__ g_m2norm) {
   int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
@@ -387,24 +388,21 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
     const CamInfo& ci = cams[c];
     if (i < ci.splat_lo || i >= ci.splat_hi) continue;
     int64_t m = ci.pair_off + (i - ci.splat_lo);
-    float g2[kGrad2d];
+    double g2[kGrad2d];
     bool any = false;
 #pragma unroll
     for (int f = 0; f < kGrad2d; ++f) {
       g2[f] = grad2d[(int64_t)f * M + m];
-      any |= (g2[f] != 0.f);
+      any |= (g2[f] != 0.0);
     }
-    if (g_m2norm) g_m2norm[m] = sqrtf(g2[0] * g2[0] + g2[1] * g2[1]);
+    if (g_m2norm) g_m2norm[m] = (float)sqrt(g2[0] * g2[0] + g2[1] * g2[1]);
     if (!any) continue;
     Geo g;
     geo_compute(ci, mu[0], mu[1], mu[2], s[0], s[1], s[2], q[0], q[1], q[2], q[3], clip, eps, g);
     go += g2[5];
-    // conic = cov^-1 : dL/dcov = -conic (dL/dconic) conic, (dL/dconic)_01 = dL/dB / 2
-    double A = g.A, B = g.B, Cc = g.C;
-    double gA = g2[2], hB = 0.5 * (double)g2[3], gC = g2[4];
-    double X00 = gA * A + hB * B, X01 = gA * B + hB * Cc;
-    double X10 = hB * A + gC * B, X11 = hB * B + gC * Cc;
-    double G00 = -(A * X00 + B * X10), G01 = -(A * X01 + B * X11), G11 = -(B * X01 + Cc * X11);
+    // the raster pass accumulates dL/dcov2d directly (entries a, b, c of
+    // [[a, b], [b, c]], b one parameter in both off-diagonal slots)
+    const double G00 = g2[2], G01 = 0.5 * (double)g2[3], G11 = g2[4];
     const double* T = g.T;
     const double* S = g.S;
     double TS0[3] = {T[0] * S[0] + T[1] * S[1] + T[2] * S[2], T[0] * S[1] + T[1] * S[3] + T[2] * S[4],
@@ -495,7 +493,7 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void project_bwd_sh_kernel(
     const CamInfo* __restrict__ cams, int C, int64_t N, const float* __restrict__ means,
-    const float* __restrict__ sh, const float* __restrict__ grad2d, int64_t M,
+    const float* __restrict__ sh, const double* __restrict__ grad2d, int64_t M,
     float* __restrict__ g_sh, float* __restrict__ g_means) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
@@ -512,8 +510,8 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_sh_kernel(
     const CamInfo& ci = cams[c];
     if (i < ci.splat_lo || i >= ci.splat_hi) continue;
     const int64_t m = ci.pair_off + (i - ci.splat_lo);
-    const float gr = grad2d[6 * M + m], gg = grad2d[7 * M + m], gb = grad2d[8 * M + m];
-    if (gr == 0.f && gg == 0.f && gb == 0.f) continue;
+    const double gr = grad2d[6 * M + m], gg = grad2d[7 * M + m], gb = grad2d[8 * M + m];
+    if (gr == 0.0 && gg == 0.0 && gb == 0.0) continue;
     double vx = mu0 - ci.campos[0], vy = mu1 - ci.campos[1], vz = mu2 - ci.campos[2];
     double inv = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
     double dx = vx * inv, dy = vy * inv, dz = vz * inv;
@@ -603,13 +601,13 @@ hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_spla
       ProfScope ps("project_bwd", s);                                                              \
       hipLaunchKernelGGL(project_bwd_kernel<D>, grid, dim3(kProjThreads), 0, s, cams, p.C, p.N,   \
                          sp->means, sp->scales, sp->quats, sp->sh, cfg->eps2d, cfg->clip,         \
-                         (const float*)(ws + p.lay.grad2d), p.M, gr->means, gr->scales,           \
+                         (const double*)(ws + p.lay.grad2d), p.M, gr->means, gr->scales,          \
                          gr->quats, gr->opacity, gr->mean2d_norm);                                \
     }                                                                                              \
     {                                                                                              \
       ProfScope ps("project_bwd_sh", s);                                                           \
       hipLaunchKernelGGL(project_bwd_sh_kernel<D>, grid, dim3(kProjThreads), 0, s, cams, p.C, p.N, \
-                         sp->means, sp->sh, (const float*)(ws + p.lay.grad2d), p.M, gr->sh,       \
+                         sp->means, sp->sh, (const double*)(ws + p.lay.grad2d), p.M, gr->sh,      \
                          gr->means);                                                              \
     }                                                                                              \
   } while (0)

@@ -46,10 +46,22 @@ struct PairEval {
   bool clamped;
 };
 
+// sqrt(q) for q >= 0 (a negative q, possible only by rounding of the
+// expanded quadratic form at a splat's centre, counts as 0): the FP32
+// reciprocal square root as a start and one FP64 Newton step, which brings
+// the relative error from about 2^-22 to below 1e-13.  Below 1e-30 the result
+// is 0 (an absolute error under 1e-15).
+__device__ __forceinline__ double sqrt_nonneg(double q) {
+  if (!(q > 1e-30)) return 0.0;
+  const double y = (double)__builtin_amdgcn_rsqf((float)q);
+  const double d0 = q * y;
+  return fma(0.5 * y, fma(-d0, d0, q), d0);
+}
+
 __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterParams& rp) {
 #pragma clang fp contract(off)
   PairEval e;
-  e.D = sqrt(q);
+  e.D = sqrt_nonneg(q);
   const double t = o * (e.D * rp.inv_lam);
   e.alpha = o - t;
   e.oma = (1.0 - o) + t;
@@ -61,8 +73,8 @@ __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterPa
   return e;
 }
 
-// 1/x in FP64 from the hardware estimate and two Newton steps (for x in
-// [1e-3, 1e3] the result is within an ulp or two of the rounded quotient).
+// 1/x in FP64 from the hardware estimate and two Newton steps (for normal,
+// positive x the result is within an ulp or two of the rounded quotient).
 __device__ __forceinline__ double rcp_d(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -94,14 +106,15 @@ __device__ __forceinline__ int cam_of_tile(const CamInfo* cams, int C, int64_t t
 // five FP64 FMAs per pixel.  Entries whose support ellipse misses the tile's
 // pixel-centre rectangle are dropped and the survivors compacted in list
 // order, so the per-pixel loop only sees splats that can touch the tile.
-template <int NT>
+// NS staged entries at most; NW waves in the block
+template <int NS, int NW>
 struct Stage {
-  double qa[NT], qb[NT], qc[NT], qd[NT], qe[NT], qf[NT];
-  double ox[NT], oy[NT];     // centre relative to the tile's first pixel centre
-  float r[NT], g[NT], b[NT], o[NT];
-  int32_t pos[NT];           // position in the tile list
-  uint32_t m[NT];            // pair id
-  int32_t wcount[NT / 64];
+  double qa[NS], qb[NS], qc[NS], qd[NS], qe[NS], qf[NS];
+  double ox[NS], oy[NS];     // centre relative to the tile's first pixel centre
+  float r[NS], g[NS], b[NS], o[NS];
+  int32_t pos[NS];           // position in the tile list
+  uint32_t m[NS];            // pair id
+  int32_t wcount[NW];
 };
 
 __device__ __forceinline__ double quad_local(double qa, double qb, double qc, double qd, double qe,
@@ -137,8 +150,8 @@ __device__ __forceinline__ bool ellipse_hits_rect(double ox, double oy, double A
 // Stage one batch: thread i (i < NT) brings entry `vidx` of the sorted
 // values (if `has`), whose position in the tile's list is `gpos`.  Returns the
 // number of surviving entries (block-uniform).
-template <int TW, int TH>
-__device__ __forceinline__ int stage_batch(Stage<TW * TH>& st, const uint32_t* __restrict__ vals,
+template <int TW, int TH, int NS>
+__device__ __forceinline__ int stage_batch(Stage<NS, TW * TH / 64>& st, const uint32_t* __restrict__ vals,
                                            const ProjRec* __restrict__ proj, int64_t M, bool has,
                                            int64_t vidx, int32_t gpos, double x0c, double y0c,
                                            double lam2) {
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
     float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ last,
     uint32_t* __restrict__ tile_contrib) {
   constexpr int NT = TW * TH;
-  __shared__ Stage<NT> st;
+  __shared__ Stage<NT, NT / 64> st;
   __shared__ uint32_t s_cnt[NT / 64];
   const int tid = threadIdx.x;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -244,7 +257,7 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   for (int32_t p0 = 0; p0 < len; p0 += batch) {
     if (__syncthreads_count(!done) == 0) break;
     const int nb = (len - p0) < batch ? (len - p0) : batch;
-    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, tid < nb, start + p0 + tid,
+    const int cnt = stage_batch<TW, TH, NT>(st, vals, proj, M, tid < nb, start + p0 + tid,
                                         prefix + p0 + tid, x0c, y0c, rp.lam2);
     if (!done) {
       for (int k = 0; k < cnt; ++k) {
@@ -304,11 +317,14 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
     RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
-    float* __restrict__ grad2d) {
+    double* __restrict__ grad2d) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
-  __shared__ Stage<NT> st;
-  __shared__ float s_acc[NT][kGrad2d];   // per staged entry; odd stride, no bank conflicts
+  // at most 128 entries per batch, so that the FP64 accumulators fit beside
+  // the staged entries without lowering the occupancy
+  constexpr int NS = NT < 128 ? NT : 128;
+  __shared__ Stage<NS, NW> st;
+  __shared__ double s_acc[NS][kGrad2d];   // per staged entry
   __shared__ int32_t s_max[NW];
   __shared__ int64_t s_segbase[kMaxDepthChunks];
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
@@ -369,8 +385,9 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
 #pragma unroll
   for (int w = 0; w < NW; ++w) maxlast = s_max[w] > maxlast ? s_max[w] : maxlast;
 
-  for (int32_t hi = maxlast; hi > 0; hi -= batch) {
-    const int32_t lo = hi - batch > 0 ? hi - batch : 0;
+  const int bsz = batch < NS ? batch : NS;
+  for (int32_t hi = maxlast; hi > 0; hi -= bsz) {
+    const int32_t lo = hi - bsz > 0 ? hi - bsz : 0;
     __syncthreads();
     const int32_t q = lo + tid;
     int64_t vidx = 0;
@@ -379,13 +396,13 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
       while (cc + 1 < K && s_segpre[cc + 1] <= q) ++cc;
       vidx = s_segbase[cc] + (q - s_segpre[cc]);
     }
-    const int cnt = stage_batch<TW, TH>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.lam2);
-    for (int i = tid; i < kGrad2d * NT; i += NT) (&s_acc[0][0])[i] = 0.f;
+    const int cnt = stage_batch<TW, TH, NS>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.lam2);
+    for (int i = tid; i < kGrad2d * NS; i += NT) (&s_acc[0][0])[i] = 0.0;
     __syncthreads();
     for (int k = cnt - 1; k >= 0; --k) {
-      float gv[kGrad2d];
+      double gv[kGrad2d];
 #pragma unroll
-      for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.f;
+      for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.0;
       bool contrib = false;
       if (st.pos[k] < mylast) {
         const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
@@ -408,31 +425,34 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
             S1 = fma(cg, w, S1);
             S2 = fma(cb, w, S2);
             T = Ti;
-            const float wf = (float)w;
-            float g_r = wf * (float)G0, g_g = wf * (float)G1, g_b = wf * (float)G2;
-            const float dLdaf = (float)dLda;
-            const float Df = (float)e.D;
-            const float Dl = Df * rp.inv_lam_f;
-            float om = 1.f;
+            // the per-pair terms and their sums over the tile's pixels in FP64
+            double g_r = w * G0, g_g = w * G1, g_b = w * G2;
+            double om = 1.0;
             if (rp.ags) {
-              const float arg = rp.ags_arg ? Dl : Df;
-              om = __expf(-arg * arg);
+              const double arg = rp.ags_arg ? e.D * rp.inv_lam : e.D;
+              om = exp(-arg * arg);
             }
-            float g_o = 0.f;
+            double g_o = 0.0;
             if (!e.clamped) {
-              g_o = (1.f - Dl) * dLdaf;
-              const float dLdD = -(st.o[k] * dLdaf) * rp.inv_lam_f * om;
+              g_o = (1.0 - e.D * rp.inv_lam) * dLda;
+              const double dLdD = -(o * dLda) * rp.inv_lam * om;
               if (e.D > 0.0) {
-                const float gq = 0.5f * dLdD * __builtin_amdgcn_rcpf(Df);
+                // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
+                // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not
+                // the conic) is what the projection backward differentiates,
+                // so its gradient is summed here: going through the inverse
+                // after the FP32 sum would amplify the sum's rounding for
+                // elongated splats.
+                const double gq = 0.5 * dLdD * rcp_d(e.D);
                 const double dx = lx - st.ox[k], dy = ly - st.oy[k];
                 const double A = st.qa[k], B = 0.5 * st.qb[k], Cc = st.qc[k];
-                const float gx = (float)(A * dx + B * dy), gy = (float)(B * dx + Cc * dy);
-                const float fdx = (float)dx, fdy = (float)dy;
-                gv[0] = -2.f * gq * gx;
-                gv[1] = -2.f * gq * gy;
-                gv[2] = gq * fdx * fdx;
-                gv[3] = 2.f * gq * fdx * fdy;
-                gv[4] = gq * fdy * fdy;
+                const double ux = A * dx + B * dy, uy = B * dx + Cc * dy;
+                const double gux = gq * ux, guy = gq * uy;
+                gv[0] = -2.0 * gux;
+                gv[1] = -2.0 * guy;
+                gv[2] = -gux * ux;
+                gv[3] = -2.0 * gux * uy;
+                gv[4] = -guy * uy;
               }
             }
             if (rp.ags_scope) {
@@ -448,13 +468,13 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
           }
         }
       }
-      // wave-wide sums (all lanes active here), one LDS add per wave
+      // wave-wide FP64 sums (all lanes active here), one LDS add per wave
       if (__builtin_amdgcn_ballot_w64(contrib) != 0ull) {
         static_assert(kGrad2d == 9, "eight fields summed together, one alone");
-        const float s8 = wave_sum8(gv, lane);
-        if ((lane & 7) == 0 && s8 != 0.f) atomicAdd(&s_acc[k][wave_sum8_field(lane >> 3)], s8);
-        const float s1 = wave_sum_to_lane63(gv[8]);
-        if (lane == 63 && s1 != 0.f) atomicAdd(&s_acc[k][8], s1);
+        const double s8 = wave_sum8_d(gv, lane);
+        if ((lane & 7) == 0 && s8 != 0.0) atomicAdd(&s_acc[k][wave_sum8_field(lane >> 3)], s8);
+        const double s1 = wave_sum_to_lane63_d(gv[8]);
+        if (lane == 63 && s1 != 0.0) atomicAdd(&s_acc[k][8], s1);
       }
     }
     __syncthreads();
@@ -462,8 +482,8 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
       const int64_t m = (int64_t)st.m[tid];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) {
-        const float v = s_acc[tid][f];
-        if (v != 0.f) unsafeAtomicAdd(grad2d + (int64_t)f * M + m, v);
+        const double v = s_acc[tid][f];
+        if (v != 0.0) unsafeAtomicAdd(grad2d + (int64_t)f * M + m, v);
       }
     }
   }
@@ -541,12 +561,12 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
 hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                              const float* final_T, const int32_t* last, const float* dL_dimage,
                              const float* dL_dalpha, const ls_grads* g, hipStream_t s) {
-  float* grad2d = (float*)(ws + p.lay.grad2d);
-  const int64_t ng = (int64_t)kGrad2d * p.M;
+  double* grad2d = (double*)(ws + p.lay.grad2d);
+  const int64_t ng = 2 * (int64_t)kGrad2d * p.M;   // as float words
   if (ng > 0) {
     int64_t blocks = std::min<int64_t>((ng + 255) / 256, 8192);
     ProfScope ps("zero_grad2d", s);
-    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, grad2d, ng);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (float*)grad2d, ng);
   }
   if (p.T > 0) {
     const CamInfo* cams = (const CamInfo*)(ws + p.lay.cams);

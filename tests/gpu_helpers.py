@@ -94,8 +94,9 @@ def rms(x):
     return math.sqrt(float(np.mean(x * x))) if x.size else 0.0
 
 
-def assert_close(name, x, ref, rel=REL, mask=None):
-    """Normwise and RMS-floored elementwise relative error bound."""
+def assert_close(name, x, ref, rel=REL, mask=None, elementwise=True):
+    """Normwise and (unless `elementwise` is False) RMS-floored elementwise
+    relative error bound."""
     x = np.asarray(x, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
     if mask is not None:
@@ -115,6 +116,8 @@ def assert_close(name, x, ref, rel=REL, mask=None):
     worst = np.max(err / np.maximum(floor / rel, 1e-300))
     say(f"  {name}: n={ref.size} normwise={normwise:.2e} worst_elem_ratio={worst:.2e}")
     assert normwise <= rel, f"{name}: normwise error {normwise:.3e} > {rel}"
+    if not elementwise:
+        return
     bad = err > floor
     assert not bad.any(), (f"{name}: {bad.sum()} elements exceed the bound; worst at "
                            f"{np.argmax(err - floor)}: got {x[np.argmax(err - floor)]!r} "

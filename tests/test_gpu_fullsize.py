@@ -17,8 +17,11 @@ checks
     plain-definition list that reaches every pixel's last contributor), the
     projected records the composite reads, the composite (image, final_T,
     last) and the tile's contribution count;
-  * the gradients of every splat for an upstream gradient that is non-zero on
-    the sampled tiles only (every other splat must receive exactly zero).
+  * the gradients for an upstream gradient that is non-zero on the sampled
+    tiles only (every other pair and splat must receive exactly zero): the
+    per-pair 2D gradients element by element; the splat gradients element by
+    element against the oracle's projection backward of the library's 2D
+    gradients, and end to end normwise.
 """
 from __future__ import annotations
 
@@ -147,18 +150,32 @@ def _sampled_parity(k, views, tiles_per_view, seed):
     say(f"  {len(tiles)} sampled tiles equal")
 
     # -- gradients ---------------------------------------------------------------
+    # Staged: (1) the per-pair 2D gradients (9 fields) element by element;
+    # (2) the splat gradients element by element against the oracle's
+    # projection backward fed with the library's own 2D gradients; (3) the
+    # splat gradients end to end, normwise.  Stage (2) separates the rounding
+    # of the FP32 per-pixel terms, which the chain through the projection can
+    # amplify where the centre and conic terms of a large splat cancel, from
+    # the projection backward itself.
     grads = rast.backward(sp, torch.from_numpy(G).cuda())
     torch.cuda.synchronize()
     got = {k: v.detach().cpu().numpy().astype(np.float64) for k, v in grads.items()}
+    g2 = rast.view("grad2d", torch.float64, 9 * M).cpu().numpy().reshape(9, M)
     K = scene.sh.shape[1]
     want = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)),
                 opacity=np.zeros(N), sh=np.zeros((N, K, 3)))
+    staged = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)),
+                  opacity=np.zeros(N), sh=np.zeros((N, K, 3)))
     touched = np.zeros(N, bool)
+    pairs_touched = np.zeros(M, bool)
+    want2 = np.zeros((9, M))
     for c in views:
         W, H = int(cams.width[c]), int(cams.height[c])
         mine = [t for t in tiles if t[0] == c]
         ids = np.unique(np.concatenate([t[2] for t in mine]))
         touched[ids] = True
+        pids = int(lay.pair_off[c]) + (ids - int(lay.splat_lo[c]))
+        pairs_touched[pids] = True
         sub = projection.project(scene.means[ids], scene.scales[ids], scene.quats[ids],
                                  scene.sh[ids], deg, cams.viewmat[c], cams.intrin[c], W, H, ocfg)
         acc = [np.zeros((len(ids), 3)), np.zeros(len(ids)), np.zeros((len(ids), 3)),
@@ -175,21 +192,33 @@ def _sampled_parity(k, views, tiles_per_view, seed):
                                        len(ids))
             for a, b in zip(acc, r):
                 a += b
-        gm, gs, gq, gsh = projection.project_backward(sub, scene.sh[ids], deg, acc[3], acc[2],
-                                                      acc[0])
-        want["means"][ids] += gm
-        want["scales"][ids] += gs
-        want["quats"][ids] += gq
-        want["opacity"][ids] += acc[1]
-        want["sh"][ids] += gsh
-    for k in ("means", "scales", "quats"):
-        assert np.all(got[k][:, ~touched] == 0.0), k
-        assert_close(f"d_{k}", got[k][:, touched].T, want[k][touched])
-    assert np.all(got["opacity"][~touched] == 0.0)
-    assert_close("d_opacity", got["opacity"][touched], want["opacity"][touched])
+        want2[0:2, pids] = acc[3].T
+        want2[2:5, pids] = projection.cov2d_grad(sub["conic"], acc[2]).T
+        want2[5, pids] = acc[1]
+        want2[6:9, pids] = acc[0].T
+        for dst, (g_rgb, g_o, g_cov, g_mu) in (
+                (want, (acc[0], acc[1], want2[2:5, pids].T, acc[3])),
+                (staged, (g2[6:9, pids].T, g2[5, pids], g2[2:5, pids].T, g2[0:2, pids].T))):
+            gm, gs, gq, gsh = projection.project_backward_cov(sub, scene.sh[ids], deg, g_mu,
+                                                              g_cov, g_rgb)
+            dst["means"][ids] += gm
+            dst["scales"][ids] += gs
+            dst["quats"][ids] += gq
+            dst["opacity"][ids] += g_o
+            dst["sh"][ids] += gsh
+    # (1) per-pair 2D gradients
+    assert np.all(g2[:, ~pairs_touched] == 0.0)
+    for name, rows in (("d_mean2d", slice(0, 2)), ("d_cov2d", slice(2, 5)),
+                       ("d_opacity2d", slice(5, 6)), ("d_rgb", slice(6, 9))):
+        assert_close(name, g2[rows, pairs_touched], want2[rows, pairs_touched])
+    # (2) staged and (3) end to end
     gsh_ = got["sh"].reshape(K, 3, N).transpose(2, 0, 1)
-    assert np.all(gsh_[~touched] == 0.0)
-    assert_close("d_sh", gsh_[touched], want["sh"][touched])
+    mine3 = dict(means=got["means"].T, scales=got["scales"].T, quats=got["quats"].T,
+                 opacity=got["opacity"], sh=gsh_)
+    for k, v in mine3.items():
+        assert np.all(v[~touched] == 0.0), k
+        assert_close(f"d_{k} (staged)", v[touched], staged[k][touched])
+        assert_close(f"d_{k}", v[touched], want[k][touched])
 
 
 def test_benchmark_configuration_sampled():
