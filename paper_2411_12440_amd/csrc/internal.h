@@ -133,11 +133,19 @@ __device__ __forceinline__ float wave_sum8(const float* v, int lane) {
 }
 
 // FP64 versions: the same lane movements applied to both 32-bit halves.
+// (A full row mask writes every lane, so no old value is needed; with a
+// partial mask the lanes outside it receive 0.)
 template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ double dpp_move_d(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, ROWMASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  int lo, hi;
+  if constexpr (ROWMASK == 0xF) {
+    lo = __builtin_amdgcn_mov_dpp((int)(b & 0xFFFFFFFFll), CTRL, ROWMASK, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, ROWMASK, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  }
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 

@@ -32,9 +32,9 @@ namespace {
 struct RasterParams {
   double lam2;        // lambda^2: D' >= lambda <=> outside the support
   double inv_lam;     // 1 / lambda
+  double inv_lam2;    // 1 / lambda^2
   double amin, amax, oma_max, tmin;
   float bg0, bg1, bg2;
-  float inv_lam_f;
   int ags, ags_arg, ags_scope;
 };
 
@@ -71,6 +71,30 @@ __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterPa
     e.oma = rp.oma_max;
   }
   return e;
+}
+
+// e^-x for x >= 0 in FP64: x = k ln2 + r with |r| <= ln2 / 2 (ln2 split in a
+// high part whose products with k are exact and a low part), e^-r from its
+// Taylor series to degree 11 (truncation below 6e-15), scaled by 2^-k.
+__device__ __forceinline__ double exp_neg(double x) {
+  if (!(x < 708.0)) return 0.0;
+  const double k = rint(x * 1.4426950408889634);
+  double r = fma(-k, 6.93147180369123816490e-01, x);
+  r = fma(-k, 1.90821492927058770002e-10, r);
+  const double t = -r;
+  double p = 1.0 / 39916800.0;
+  p = fma(p, t, 1.0 / 3628800.0);
+  p = fma(p, t, 1.0 / 362880.0);
+  p = fma(p, t, 1.0 / 40320.0);
+  p = fma(p, t, 1.0 / 5040.0);
+  p = fma(p, t, 1.0 / 720.0);
+  p = fma(p, t, 1.0 / 120.0);
+  p = fma(p, t, 1.0 / 24.0);
+  p = fma(p, t, 1.0 / 6.0);
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  return ldexp(p, -(int)k);
 }
 
 // 1/x in FP64 from the hardware estimate and two Newton steps (for normal,
@@ -400,82 +424,62 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
     for (int i = tid; i < kGrad2d * NS; i += NT) (&s_acc[0][0])[i] = 0.0;
     __syncthreads();
     for (int k = cnt - 1; k >= 0; --k) {
+      // Evaluated for every lane and masked at the end, so that the wave
+      // runs one path; a wave with no contributing lane skips the entry.
+      const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
+                                  lx, ly, lx2, lxy, ly2);
+      const double o = (double)st.o[k];
+      const PairEval e = pair_eval(q, o, rp);
+      const bool contrib = st.pos[k] < mylast && q < rp.lam2 && e.alpha > 0.0 &&
+                           e.alpha >= rp.amin;
+      if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
+      // transmittance, suffix colour and dL/dalpha (they carry the error of
+      // every step), the per-pair terms and their sums: all FP64
+      const double inv = rcp_d(e.oma);
+      const double Ti = T * inv;
+      const double w = e.alpha * Ti;
+      const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
+      const double GdC = G0 * cr + G1 * cg + G2 * cb;
+      const double GdS = G0 * S0 + G1 * S1 + G2 * S2 + GSa;
+      const double dLda = Ti * GdC - GdS * inv;
+      if (contrib) {
+        S0 = fma(cr, w, S0);
+        S1 = fma(cg, w, S1);
+        S2 = fma(cb, w, S2);
+        T = Ti;
+      }
+      double om = 1.0;
+      if (rp.ags) om = exp_neg(rp.ags_arg ? q * rp.inv_lam2 : q);
+      // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
+      // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the conic)
+      // is what the projection backward differentiates, so its gradient is
+      // summed here; going through the inverse after the sum would amplify
+      // the sum's rounding for elongated splats.
+      const bool geo = contrib && !e.clamped && e.D > 0.0;
+      const double dLdD = -(o * dLda) * rp.inv_lam * om;
+      const double gq = 0.5 * dLdD * rcp_d(e.D);
+      const double dx = lx - st.ox[k], dy = ly - st.oy[k];
+      const double A = st.qa[k], B = 0.5 * st.qb[k], Cc = st.qc[k];
+      const double ux = A * dx + B * dy, uy = B * dx + Cc * dy;
+      const double gux = gq * ux, guy = gq * uy;
+      const double sc = rp.ags_scope ? om : 1.0;
       double gv[kGrad2d];
-#pragma unroll
-      for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.0;
-      bool contrib = false;
-      if (st.pos[k] < mylast) {
-        const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
-                                    lx, ly, lx2, lxy, ly2);
-        if (q < rp.lam2) {
-          const double o = (double)st.o[k];
-          const PairEval e = pair_eval(q, o, rp);
-          if (e.alpha > 0.0 && e.alpha >= rp.amin) {
-            contrib = true;
-            // transmittance, suffix colour and dL/dalpha in FP64 (they carry
-            // the error of every step); the per-pair terms in FP32
-            const double inv = rcp_d(e.oma);
-            const double Ti = T * inv;
-            const double w = e.alpha * Ti;
-            const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
-            const double GdC = G0 * cr + G1 * cg + G2 * cb;
-            const double GdS = G0 * S0 + G1 * S1 + G2 * S2 + GSa;
-            const double dLda = Ti * GdC - GdS * inv;
-            S0 = fma(cr, w, S0);
-            S1 = fma(cg, w, S1);
-            S2 = fma(cb, w, S2);
-            T = Ti;
-            // the per-pair terms and their sums over the tile's pixels in FP64
-            double g_r = w * G0, g_g = w * G1, g_b = w * G2;
-            double om = 1.0;
-            if (rp.ags) {
-              const double arg = rp.ags_arg ? e.D * rp.inv_lam : e.D;
-              om = exp(-arg * arg);
-            }
-            double g_o = 0.0;
-            if (!e.clamped) {
-              g_o = (1.0 - e.D * rp.inv_lam) * dLda;
-              const double dLdD = -(o * dLda) * rp.inv_lam * om;
-              if (e.D > 0.0) {
-                // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
-                // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not
-                // the conic) is what the projection backward differentiates,
-                // so its gradient is summed here: going through the inverse
-                // after the FP32 sum would amplify the sum's rounding for
-                // elongated splats.
-                const double gq = 0.5 * dLdD * rcp_d(e.D);
-                const double dx = lx - st.ox[k], dy = ly - st.oy[k];
-                const double A = st.qa[k], B = 0.5 * st.qb[k], Cc = st.qc[k];
-                const double ux = A * dx + B * dy, uy = B * dx + Cc * dy;
-                const double gux = gq * ux, guy = gq * uy;
-                gv[0] = -2.0 * gux;
-                gv[1] = -2.0 * guy;
-                gv[2] = -gux * ux;
-                gv[3] = -2.0 * gux * uy;
-                gv[4] = -guy * uy;
-              }
-            }
-            if (rp.ags_scope) {
-              g_o *= om;
-              g_r *= om;
-              g_g *= om;
-              g_b *= om;
-            }
-            gv[5] = g_o;
-            gv[6] = g_r;
-            gv[7] = g_g;
-            gv[8] = g_b;
-          }
-        }
-      }
+      gv[0] = geo ? -2.0 * gux : 0.0;
+      gv[1] = geo ? -2.0 * guy : 0.0;
+      gv[2] = geo ? -gux * ux : 0.0;
+      gv[3] = geo ? -2.0 * gux * uy : 0.0;
+      gv[4] = geo ? -guy * uy : 0.0;
+      gv[5] = (contrib && !e.clamped) ? (1.0 - e.D * rp.inv_lam) * dLda * sc : 0.0;
+      const double wsc = contrib ? w * sc : 0.0;
+      gv[6] = wsc * G0;
+      gv[7] = wsc * G1;
+      gv[8] = wsc * G2;
       // wave-wide FP64 sums (all lanes active here), one LDS add per wave
-      if (__builtin_amdgcn_ballot_w64(contrib) != 0ull) {
-        static_assert(kGrad2d == 9, "eight fields summed together, one alone");
-        const double s8 = wave_sum8_d(gv, lane);
-        if ((lane & 7) == 0 && s8 != 0.0) atomicAdd(&s_acc[k][wave_sum8_field(lane >> 3)], s8);
-        const double s1 = wave_sum_to_lane63_d(gv[8]);
-        if (lane == 63 && s1 != 0.0) atomicAdd(&s_acc[k][8], s1);
-      }
+      static_assert(kGrad2d == 9, "eight fields summed together, one alone");
+      const double s8 = wave_sum8_d(gv, lane);
+      if ((lane & 7) == 0 && s8 != 0.0) atomicAdd(&s_acc[k][wave_sum8_field(lane >> 3)], s8);
+      const double s1 = wave_sum_to_lane63_d(gv[8]);
+      if (lane == 63 && s1 != 0.0) atomicAdd(&s_acc[k][8], s1);
     }
     __syncthreads();
     if (tid < cnt) {
@@ -498,7 +502,7 @@ RasterParams make_params(const ls_config* cfg) {
   RasterParams rp;
   rp.lam2 = (double)cfg->lambda * (double)cfg->lambda;
   rp.inv_lam = 1.0 / (double)cfg->lambda;
-  rp.inv_lam_f = (float)rp.inv_lam;
+  rp.inv_lam2 = rp.inv_lam * rp.inv_lam;
   rp.amin = cfg->alpha_min;
   rp.amax = cfg->alpha_max;
   rp.oma_max = 1.0 - (double)cfg->alpha_max;
