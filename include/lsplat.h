@@ -174,7 +174,8 @@ typedef struct ls_cameras {
  *   depth_key  [M] uint32: FP32 bit pattern of camera-space z (0xFFFFFFFF if
  *              culled).
  *   order      [M] uint32: pair ids sorted by (depth_key, pair id).
- *   isect_off  [M+1] int64: exclusive scan of ntiles in `order`.
+ *   isect_off  [M+1] int64: exclusive scan of ntiles in `order` (with depth
+ *              chunks only isect_off[M], the total, is written).
  *   keys       [cap] uint32: sorted global tile ids, chunk after chunk.
  *   vals       [cap] uint32: pair ids in (tile, depth, pair id) order within
  *              each chunk.

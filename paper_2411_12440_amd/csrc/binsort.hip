@@ -606,10 +606,11 @@ __device__ __forceinline__ uint32_t sat_query(const uint32_t* S, int GX, int x0,
 }
 
 // Chunk c of the depth order (pair positions [lo, hi)): for each pair the
-// number of alive tiles in its rectangle, and a mask that tells the writer
-// where they are: for a rectangle of at most kSmallRect tiles, bit j is tile j
-// (row-major) of the rectangle; a larger one gets all ones when every tile is
-// alive and 0 otherwise (then a wave of the second write kernel scans it).
+// number of alive tiles in its rectangle (from the summed-area table), and a
+// mask that tells the writer where they are: all ones when every tile is
+// alive; for a partly alive rectangle of at most kSmallRect tiles, bit j is
+// tile j (row-major) of the rectangle; 0 for a larger partly alive one (a
+// wave of the second write kernel scans it) or an empty count.
 constexpr int kSmallRect = 32;
 
 __global__ __launch_bounds__(256) void chunk_count_kernel(
@@ -627,17 +628,16 @@ __global__ __launch_bounds__(256) void chunk_count_kernel(
     uint32_t m = order[p];
     if (m >= (uint64_t)M) m = 0;
     const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
-    if (area <= (uint32_t)kSmallRect) {
+    k = sat_query(sat + ci.tile_off, ci.GX, r.x, r.y, r.z, r.w);
+    if (k == area) {
+      mask = 0xFFFFFFFFu;                  // every tile alive
+    } else if (k != 0 && area <= (uint32_t)kSmallRect) {
       int j = 0;
       for (int ty = r.y; ty <= r.w; ++ty) {
         const uint32_t* row = alive + ci.tile_off + (int64_t)ty * ci.GX;
         for (int tx = r.x; tx <= r.z; ++tx, ++j)
           if (row[tx]) mask |= 1u << j;
       }
-      k = (uint32_t)__popc(mask);
-    } else {
-      k = sat_query(sat + ci.tile_off, ci.GX, r.x, r.y, r.z, r.w);
-      mask = (k == area) ? 0xFFFFFFFFu : 0u;
     }
   }
   pcnt[p - lo] = k;
@@ -984,8 +984,10 @@ hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStr
     hipLaunchKernelGGL(scan_reduce<PairCount>, dim3(B), dim3(kScanThreads), 0, s, in, nullptr, M,
                        B, part);
     hipLaunchKernelGGL(scan_parts, dim3(1), dim3(1024), 0, s, part, B);
-    hipLaunchKernelGGL((scan_down<PairCount, PairOffsets>), dim3(B), dim3(kScanThreads), 0, s, in,
-                       out, nullptr, M, B, part);
+    // the per-pair offsets serve the complete lists; chunks need the total only
+    if (p.K == 1)
+      hipLaunchKernelGGL((scan_down<PairCount, PairOffsets>), dim3(B), dim3(kScanThreads), 0, s,
+                         in, out, nullptr, M, B, part);
     hipLaunchKernelGGL(pairs_finalize, dim3(1), dim3(64), 0, s, part + B, M, isect_off, n_isect,
                        chunk_base, chunk_n, flags, p.cap, p.n_spans, p.K == 1 ? 1 : 0);
     if ((e = hipGetLastError())) return e;

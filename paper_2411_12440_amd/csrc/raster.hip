@@ -133,8 +133,8 @@ __device__ __forceinline__ int cam_of_tile(const CamInfo* cams, int C, int64_t t
 // NS staged entries at most; NW waves in the block
 template <int NS, int NW>
 struct Stage {
+  // D'^2 at tile-local pixel (x, y) = qa x^2 + qb xy + qc y^2 + qd x + qe y + qf
   double qa[NS], qb[NS], qc[NS], qd[NS], qe[NS], qf[NS];
-  double ox[NS], oy[NS];     // centre relative to the tile's first pixel centre
   float r[NS], g[NS], b[NS], o[NS];
   int32_t pos[NS];           // position in the tile list
   uint32_t m[NS];            // pair id
@@ -214,8 +214,6 @@ __device__ __forceinline__ int stage_batch(Stage<NS, TW * TH / 64>& st, const ui
     st.qd[k] = -2.0 * u;
     st.qe[k] = -2.0 * v;
     st.qf[k] = ox * u + oy * v;
-    st.ox[k] = ox;
-    st.oy[k] = oy;
     st.r[k] = rec.r;
     st.g[k] = rec.g;
     st.b[k] = rec.b;
@@ -458,9 +456,10 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
       const bool geo = contrib && !e.clamped && e.D > 0.0;
       const double dLdD = -(o * dLda) * rp.inv_lam * om;
       const double gq = 0.5 * dLdD * rcp_d(e.D);
-      const double dx = lx - st.ox[k], dy = ly - st.oy[k];
+      // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
       const double A = st.qa[k], B = 0.5 * st.qb[k], Cc = st.qc[k];
-      const double ux = A * dx + B * dy, uy = B * dx + Cc * dy;
+      const double ux = fma(A, lx, fma(B, ly, 0.5 * st.qd[k]));
+      const double uy = fma(B, lx, fma(Cc, ly, 0.5 * st.qe[k]));
       const double gux = gq * ux, guy = gq * uy;
       const double sc = rp.ags_scope ? om : 1.0;
       double gv[kGrad2d];
