@@ -173,26 +173,43 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
     uint32_t ex = block_excl_scan_256(t, s_tmp, nullptr);
     s_base[tid] = ex + hist[(int64_t)tid * G + blockIdx.x];
   }
+  // the next tile's keys and values are loaded while this one is ranked
+  uint32_t nk[kSortItems], nv[kSortItems];
+  auto load_tile = [&](int64_t t0) {
+    const int c = (int)((end - t0) < kSortTile ? (end - t0) : kSortTile);
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const int idx = wave * (64 * kSortItems) + j * 64 + lane;
+      const bool valid = idx < c;
+      nk[j] = valid ? keys_in[t0 + idx] : 0u;
+      if (kIdentVals) nv[j] = (uint32_t)(t0 + idx);
+      else nv[j] = valid ? vals_in[t0 + idx] : 0u;
+    }
+  };
+  if (beg < end) load_tile(beg);
   for (int64_t tb = beg; tb < end; tb += kSortTile) {
     const int cnt = (int)((end - tb) < kSortTile ? (end - tb) : kSortTile);
 #pragma unroll
     for (int w = 0; w < 4; ++w) s_wcnt[w][tid] = 0;
     __syncthreads();
     uint32_t k[kSortItems], v[kSortItems], r[kSortItems], lead[kSortItems], base[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      k[j] = nk[j];
+      v[j] = nv[j];
+    }
+    if (tb + kSortTile < end) load_tile(tb + kSortTile);
     // Rank every key among the wave's keys of the same digit: ballot matching
     // finds the lanes that share the digit; the lowest of them (the leader)
     // adds the group's size to the wave's running count of that digit with
-    // an LDS atomic that returns the count before the add.  The 16 atomics
+    // an LDS atomic that returns the count before the add.  The atomics
     // do not wait for each other (one wave's LDS operations complete in
     // order), and the leaders' results are broadcast afterwards.
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       const int idx = wave * (64 * kSortItems) + j * 64 + lane;
       const bool valid = idx < cnt;
-      uint32_t key = valid ? keys_in[tb + idx] : 0u;
-      uint32_t val;
-      if (kIdentVals) val = (uint32_t)(tb + idx);
-      else val = valid ? vals_in[tb + idx] : 0u;
+      const uint32_t key = k[j];
       const uint32_t d = (key >> shift) & 255u;
       uint64_t m = __builtin_amdgcn_ballot_w64(valid);
 #pragma unroll
@@ -207,8 +224,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep(
       base[j] = 0;
       if (valid && pre == 0) base[j] = atomicAdd(&s_wcnt[wave][d], (uint32_t)__popcll(m));
       lead[j] = m ? (uint32_t)__builtin_ctzll(m) : 0u;
-      k[j] = key;
-      v[j] = val;
       r[j] = pre;
     }
 #pragma unroll

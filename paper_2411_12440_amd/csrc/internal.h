@@ -70,9 +70,10 @@ struct Plan {
   int32_t scan_blocks = 0;
 };
 
-// Radix sort geometry: 256 threads, 16 keys per thread per tile.
+// Radix sort geometry: 256 threads, 8 keys per thread per tile; at most 1024
+// blocks (four per compute unit, all resident at once).
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kMaxSortBlocks = 1024;
 constexpr int kScanThreads = 256;
