@@ -62,7 +62,7 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   ls_status st = check_config(cfg);
   if (st != LS_OK) return st;
   if (!cams) return fail(LS_ERR_INVALID_ARG, "cams is NULL");
-  if (cams->n_cams < 1 || cams->n_cams > 65536) return fail(LS_ERR_INVALID_ARG, "n_cams must be 1..65536");
+  if (cams->n_cams < 1 || cams->n_cams > 65535) return fail(LS_ERR_INVALID_ARG, "n_cams must be 1..65535");
   if (cams->n_scenes < 1) return fail(LS_ERR_INVALID_ARG, "n_scenes must be >= 1");
   if (!cams->h_width || !cams->h_height || !cams->h_scene_of_cam || !cams->h_scene_splat_off)
     return fail(LS_ERR_INVALID_ARG, "camera host arrays must not be NULL");

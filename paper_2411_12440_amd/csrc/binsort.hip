@@ -588,27 +588,52 @@ __global__ __launch_bounds__(kKeygenThreads) void keygen_kernel(
 // Per-camera inclusive summed-area table of the alive flags (one block per
 // camera): sat[t] counts the alive tiles in the rectangle from the camera's
 // first tile to t.
-__global__ __launch_bounds__(256) void alive_sat_kernel(const CamInfo* __restrict__ cams,
-                                                        const uint32_t* __restrict__ alive,
-                                                        uint32_t* __restrict__ sat) {
-  const CamInfo& ci = cams[blockIdx.x];
-  const int GX = ci.GX, GY = ci.GY;
-  uint32_t* S = sat + ci.tile_off;
-  const uint32_t* A = alive + ci.tile_off;
-  for (int r = threadIdx.x; r < GY; r += blockDim.x) {
-    uint32_t run = 0;
-    for (int x = 0; x < GX; ++x) {
-      run += A[(int64_t)r * GX + x] ? 1u : 0u;
-      S[(int64_t)r * GX + x] = run;
-    }
+// inclusive prefix sum over a wave (lane i receives x_0 + ... + x_i)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
   }
-  __syncthreads();
-  for (int x = threadIdx.x; x < GX; x += blockDim.x) {
-    uint32_t run = 0;
-    for (int r = 0; r < GY; ++r) {
-      run += S[(int64_t)r * GX + x];
-      S[(int64_t)r * GX + x] = run;
-    }
+  return x;
+}
+
+// Per-camera inclusive summed-area table of the alive flags, in two passes of
+// one wave per line: prefix sums along each tile row, then down each tile
+// column.  Grid: (ceil(max lines / 4), cameras), 4 waves per block.
+__global__ __launch_bounds__(256) void alive_sat_rows(const CamInfo* __restrict__ cams,
+                                                      const uint32_t* __restrict__ alive,
+                                                      uint32_t* __restrict__ sat) {
+  const CamInfo& ci = cams[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= ci.GY) return;
+  const uint32_t* A = alive + ci.tile_off + (int64_t)r * ci.GX;
+  uint32_t* S = sat + ci.tile_off + (int64_t)r * ci.GX;
+  uint32_t carry = 0;
+  for (int x0 = 0; x0 < ci.GX; x0 += 64) {
+    const int x = x0 + lane;
+    const uint32_t v = (x < ci.GX && A[x] != 0u) ? 1u : 0u;
+    const uint32_t inc = wave_incl_scan(v, lane) + carry;
+    if (x < ci.GX) S[x] = inc;
+    carry = __shfl(inc, 63, 64);
+  }
+}
+
+__global__ __launch_bounds__(256) void alive_sat_cols(const CamInfo* __restrict__ cams,
+                                                      uint32_t* __restrict__ sat) {
+  const CamInfo& ci = cams[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int x = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (x >= ci.GX) return;
+  uint32_t* S = sat + ci.tile_off + x;
+  uint32_t carry = 0;
+  for (int y0 = 0; y0 < ci.GY; y0 += 64) {
+    const int y = y0 + lane;
+    const uint32_t v = y < ci.GY ? S[(int64_t)y * ci.GX] : 0u;
+    const uint32_t inc = wave_incl_scan(v, lane) + carry;
+    if (y < ci.GY) S[(int64_t)y * ci.GX] = inc;
+    carry = __shfl(inc, 63, 64);
   }
 }
 
@@ -1049,7 +1074,15 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
     const unsigned grid = (unsigned)((n + 255) / 256);
     {
       ProfScope ps("chunk_count", s);
-      hipLaunchKernelGGL(alive_sat_kernel, dim3(p.C), dim3(256), 0, s, cams, alive, sat);
+      int gxm = 1, gym = 1;
+      for (int q = 0; q < p.C; ++q) {
+        gxm = std::max(gxm, p.GX[q]);
+        gym = std::max(gym, p.GY[q]);
+      }
+      hipLaunchKernelGGL(alive_sat_rows, dim3((unsigned)((gym + 3) / 4), (unsigned)p.C), dim3(256),
+                         0, s, cams, alive, sat);
+      hipLaunchKernelGGL(alive_sat_cols, dim3((unsigned)((gxm + 3) / 4), (unsigned)p.C), dim3(256),
+                         0, s, cams, sat);
       hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams, p.C,
                          M, lo, hi, sat, alive, flags, pcnt, pmask);
     }
