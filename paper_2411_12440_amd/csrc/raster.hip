@@ -141,10 +141,12 @@ struct Stage {
   int32_t wcount[NW];
 };
 
+// D'^2 at tile-local pixel (x, y), nested as
+// qf + x (qd + qa x + qb y) + y (qe + qc y): five FMA and no per-pixel squares.
+// The forward and backward kernels share it, so they take the same decisions.
 __device__ __forceinline__ double quad_local(double qa, double qb, double qc, double qd, double qe,
-                                             double qf, double lx, double ly, double lx2,
-                                             double lxy, double ly2) {
-  return fma(qa, lx2, fma(qb, lxy, fma(qc, ly2, fma(qd, lx, fma(qe, ly, qf)))));
+                                             double qf, double x, double y) {
+  return fma(x, fma(qa, x, fma(qb, y, qd)), fma(y, fma(qc, y, qe), qf));
 }
 
 // true if min over [0, w] x [0, h] of A dx^2 + 2B dx dy + C dy^2 (dx = x - ox,
@@ -174,12 +176,11 @@ __device__ __forceinline__ bool ellipse_hits_rect(double ox, double oy, double A
 // Stage one batch: thread i (i < NT) brings entry `vidx` of the sorted
 // values (if `has`), whose position in the tile's list is `gpos`.  Returns the
 // number of surviving entries (block-uniform).
-template <int TW, int TH, int NS>
-__device__ __forceinline__ int stage_batch(Stage<NS, TW * TH / 64>& st, const uint32_t* __restrict__ vals,
+template <int TW, int TH, int NS, int NWB>
+__device__ __forceinline__ int stage_batch(Stage<NS, NWB>& st, const uint32_t* __restrict__ vals,
                                            const ProjRec* __restrict__ proj, int64_t M, bool has,
                                            int64_t vidx, int32_t gpos, double x0c, double y0c,
                                            double lam2) {
-  constexpr int NT = TW * TH;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool keep = false;
   uint32_t m = 0;
@@ -198,7 +199,7 @@ __device__ __forceinline__ int stage_batch(Stage<NS, TW * TH / 64>& st, const ui
   __syncthreads();
   int base = 0, total = 0;
 #pragma unroll
-  for (int w = 0; w < NT / 64; ++w) {
+  for (int w = 0; w < NWB; ++w) {
     const int c = st.wcount[w];
     base += (w < wave) ? c : 0;
     total += c;
@@ -260,7 +261,6 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   const bool inside = (px < ci.W) && (py < ci.H);
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
   const double lx = (double)lxi, ly = (double)lyi;
-  const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
   const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
 
   double T = 1.0, cr = 0.0, cg = 0.0, cb = 0.0;
@@ -279,12 +279,12 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   for (int32_t p0 = 0; p0 < len; p0 += batch) {
     if (__syncthreads_count(!done) == 0) break;
     const int nb = (len - p0) < batch ? (len - p0) : batch;
-    const int cnt = stage_batch<TW, TH, NT>(st, vals, proj, M, tid < nb, start + p0 + tid,
+    const int cnt = stage_batch<TW, TH, NT, NT / 64>(st, vals, proj, M, tid < nb, start + p0 + tid,
                                         prefix + p0 + tid, x0c, y0c, rp.lam2);
     if (!done) {
       for (int k = 0; k < cnt; ++k) {
         const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
-                                    lx, ly, lx2, lxy, ly2);
+                                    lx, ly);
         if (!(q < rp.lam2)) continue;
         const PairEval e = pair_eval(q, (double)st.o[k], rp);
         if (!(e.alpha > 0.0) || e.alpha < rp.amin) continue;
@@ -332,22 +332,31 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   }
 }
 
+// Backward threads: a tile of 128 or more pixels gives each lane two
+// vertically adjacent pixels, so one wave-wide reduction and one read of the
+// staged entry serve both.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
+constexpr int bwd_ppl() { return TW * TH >= 128 ? 2 : 1; }
+template <int TW, int TH>
+constexpr int bwd_threads() { return TW * TH / bwd_ppl<TW, TH>(); }
+
+template <int TW, int TH>
+__global__ __launch_bounds__((bwd_threads<TW, TH>())) void raster_bwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all,
     int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
     RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
     double* __restrict__ grad2d) {
-  constexpr int NT = TW * TH;
-  constexpr int NW = NT / 64;
+  constexpr int PPL = bwd_ppl<TW, TH>();
+  constexpr int NTB = bwd_threads<TW, TH>();
+  constexpr int NWB = NTB / 64;
   // at most 128 entries per batch, so that the FP64 accumulators fit beside
   // the staged entries without lowering the occupancy
-  constexpr int NS = NT < 128 ? NT : 128;
-  __shared__ Stage<NS, NW> st;
+  constexpr int NS = NTB < 128 ? NTB : 128;
+  __shared__ Stage<NS, NWB> st;
   __shared__ double s_acc[NS][kGrad2d];   // per staged entry
-  __shared__ int32_t s_max[NW];
+  __shared__ int32_t s_max[NWB];
   __shared__ int64_t s_segbase[kMaxDepthChunks];
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -356,12 +365,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   const CamInfo& ci = cams[c];
   const int64_t local = tile - ci.tile_off;
   const int ty = (int)(local / ci.GX), tx = (int)(local % ci.GX);
-  const int lxi = tid % TW, lyi = tid / TW;
-  const int px = tx * TW + lxi, py = ty * TH + lyi;
-  const bool inside = (px < ci.W) && (py < ci.H);
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
-  const double lx = (double)lxi, ly = (double)lyi;
-  const double lx2 = lx * lx, lxy = lx * ly, ly2 = ly * ly;
   // the tile's list: its segments of every chunk, in chunk order
   if (tid == 0) {
     int32_t pre = 0;
@@ -376,27 +380,43 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   __syncthreads();
   const int64_t len = s_segpre[K];
 
-  double T = 1.0, G0 = 0.0, G1 = 0.0, G2 = 0.0, GA = 0.0;
-  int32_t mylast = 0;
-  if (inside) {
-    const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
-    const int64_t plane = (int64_t)ci.W * ci.H;
-    const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
-    T = final_T[pix];
-    mylast = last[pix];
-    mylast = mylast < 0 ? 0 : (mylast > len ? (int32_t)len : mylast);
-    G0 = dL_dimage[ib];
-    G1 = dL_dimage[ib + plane];
-    G2 = dL_dimage[ib + 2 * plane];
-    if (dL_dalpha) GA = dL_dalpha[pix];
+  // per pixel of this lane: position, upstream gradients, transmittance and
+  // the suffix colour behind the current splat (from the background term)
+  const int lxi = tid % TW;
+  double lx = (double)lxi, ly[PPL];
+  double T[PPL], G0[PPL], G1[PPL], G2[PPL], GSa[PPL], S0[PPL], S1[PPL], S2[PPL];
+  int32_t mylast[PPL];
+  int32_t mx = 0;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int lyi = (tid / TW) * PPL + j;
+    ly[j] = (double)lyi;
+    const int px = tx * TW + lxi, py = ty * TH + lyi;
+    T[j] = 1.0;
+    G0[j] = G1[j] = G2[j] = 0.0;
+    double GA = 0.0;
+    mylast[j] = 0;
+    if (px < ci.W && py < ci.H) {
+      const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
+      const int64_t plane = (int64_t)ci.W * ci.H;
+      const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
+      T[j] = final_T[pix];
+      const int32_t l = last[pix];
+      mylast[j] = l < 0 ? 0 : (l > len ? (int32_t)len : l);
+      G0[j] = dL_dimage[ib];
+      G1[j] = dL_dimage[ib + plane];
+      G2[j] = dL_dimage[ib + 2 * plane];
+      if (dL_dalpha) GA = dL_dalpha[pix];
+    }
+    S0[j] = T[j] * (double)rp.bg0;
+    S1[j] = T[j] * (double)rp.bg1;
+    S2[j] = T[j] * (double)rp.bg2;
+    // the accumulated opacity 1 - T_final as a fourth channel: splat colours
+    // 0, background -1, so its suffix term is the constant -T_final
+    GSa[j] = -GA * T[j];
+    mx = mylast[j] > mx ? mylast[j] : mx;
   }
-  // suffix colour behind the current splat, starting with the background term
-  double S0 = T * (double)rp.bg0, S1 = T * (double)rp.bg1, S2 = T * (double)rp.bg2;
-  // the accumulated opacity 1 - T_final as a fourth channel: splat colours 0,
-  // background -1, so its suffix term is the constant -T_final
-  const double GSa = -GA * T;
   // tile-wide maximum of `last`
-  int32_t mx = mylast;
   for (int d = 32; d > 0; d >>= 1) {
     int32_t y = __shfl_xor(mx, d, 64);
     mx = y > mx ? y : mx;
@@ -405,7 +425,7 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
   __syncthreads();
   int32_t maxlast = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) maxlast = s_max[w] > maxlast ? s_max[w] : maxlast;
+  for (int w = 0; w < NWB; ++w) maxlast = s_max[w] > maxlast ? s_max[w] : maxlast;
 
   const int bsz = batch < NS ? batch : NS;
   for (int32_t hi = maxlast; hi > 0; hi -= bsz) {
@@ -418,61 +438,79 @@ __global__ __launch_bounds__(TW* TH) void raster_bwd_kernel(
       while (cc + 1 < K && s_segpre[cc + 1] <= q) ++cc;
       vidx = s_segbase[cc] + (q - s_segpre[cc]);
     }
-    const int cnt = stage_batch<TW, TH, NS>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.lam2);
-    for (int i = tid; i < kGrad2d * NS; i += NT) (&s_acc[0][0])[i] = 0.0;
+    const int cnt =
+        stage_batch<TW, TH, NS, NWB>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.lam2);
+    for (int i = tid; i < kGrad2d * NS; i += NTB) (&s_acc[0][0])[i] = 0.0;
     __syncthreads();
     for (int k = cnt - 1; k >= 0; --k) {
       // Evaluated for every lane and masked at the end, so that the wave
-      // runs one path; a wave with no contributing lane skips the entry.
-      const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
-                                  lx, ly, lx2, lxy, ly2);
+      // runs one path; a wave with no contributing pixel skips the entry.
+      const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
+      const double qd = st.qd[k], qe = st.qe[k], qf = st.qf[k];
+      const int32_t pos = st.pos[k];
       const double o = (double)st.o[k];
-      const PairEval e = pair_eval(q, o, rp);
-      const bool contrib = st.pos[k] < mylast && q < rp.lam2 && e.alpha > 0.0 &&
-                           e.alpha >= rp.amin;
-      if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
-      // transmittance, suffix colour and dL/dalpha (they carry the error of
-      // every step), the per-pair terms and their sums: all FP64
-      const double inv = rcp_d(e.oma);
-      const double Ti = T * inv;
-      const double w = e.alpha * Ti;
-      const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
-      const double GdC = G0 * cr + G1 * cg + G2 * cb;
-      const double GdS = G0 * S0 + G1 * S1 + G2 * S2 + GSa;
-      const double dLda = Ti * GdC - GdS * inv;
-      if (contrib) {
-        S0 = fma(cr, w, S0);
-        S1 = fma(cg, w, S1);
-        S2 = fma(cb, w, S2);
-        T = Ti;
+      double qq[PPL];
+      PairEval e[PPL];
+      bool contrib[PPL];
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        qq[j] = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
+        e[j] = pair_eval(qq[j], o, rp);
+        contrib[j] = pos < mylast[j] && qq[j] < rp.lam2 && e[j].alpha > 0.0 &&
+                     e[j].alpha >= rp.amin;
+        any = any || contrib[j];
       }
-      double om = 1.0;
-      if (rp.ags) om = exp_neg(rp.ags_arg ? q * rp.inv_lam2 : q);
-      // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
-      // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the conic)
-      // is what the projection backward differentiates, so its gradient is
-      // summed here; going through the inverse after the sum would amplify
-      // the sum's rounding for elongated splats.
-      const bool geo = contrib && !e.clamped && e.D > 0.0;
-      const double dLdD = -(o * dLda) * rp.inv_lam * om;
-      const double gq = 0.5 * dLdD * rcp_d(e.D);
-      // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
-      const double A = st.qa[k], B = 0.5 * st.qb[k], Cc = st.qc[k];
-      const double ux = fma(A, lx, fma(B, ly, 0.5 * st.qd[k]));
-      const double uy = fma(B, lx, fma(Cc, ly, 0.5 * st.qe[k]));
-      const double gux = gq * ux, guy = gq * uy;
-      const double sc = rp.ags_scope ? om : 1.0;
+      if (__builtin_amdgcn_ballot_w64(any) == 0ull) continue;
+      const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
+      const double A = qa, B = 0.5 * qb, Cc = qc;
       double gv[kGrad2d];
-      gv[0] = geo ? -2.0 * gux : 0.0;
-      gv[1] = geo ? -2.0 * guy : 0.0;
-      gv[2] = geo ? -gux * ux : 0.0;
-      gv[3] = geo ? -2.0 * gux * uy : 0.0;
-      gv[4] = geo ? -guy * uy : 0.0;
-      gv[5] = (contrib && !e.clamped) ? (1.0 - e.D * rp.inv_lam) * dLda * sc : 0.0;
-      const double wsc = contrib ? w * sc : 0.0;
-      gv[6] = wsc * G0;
-      gv[7] = wsc * G1;
-      gv[8] = wsc * G2;
+#pragma unroll
+      for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.0;
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        // transmittance, suffix colour and dL/dalpha (they carry the error
+        // of every step), the per-pair terms and their sums: all FP64
+        const double inv = rcp_d(e[j].oma);
+        const double Ti = T[j] * inv;
+        const double w = e[j].alpha * Ti;
+        const double GdC = G0[j] * cr + G1[j] * cg + G2[j] * cb;
+        const double GdS = G0[j] * S0[j] + G1[j] * S1[j] + G2[j] * S2[j] + GSa[j];
+        const double dLda = Ti * GdC - GdS * inv;
+        if (contrib[j]) {
+          S0[j] = fma(cr, w, S0[j]);
+          S1[j] = fma(cg, w, S1[j]);
+          S2[j] = fma(cb, w, S2[j]);
+          T[j] = Ti;
+        }
+        double om = 1.0;
+        if (rp.ags) om = exp_neg(rp.ags_arg ? qq[j] * rp.inv_lam2 : qq[j]);
+        // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
+        // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the
+        // conic) is what the projection backward differentiates, so its
+        // gradient is summed here; going through the inverse after the sum
+        // would amplify the sum's rounding for elongated splats.
+        const bool geo = contrib[j] && !e[j].clamped && e[j].D > 0.0;
+        const double dLdD = -(o * dLda) * rp.inv_lam * om;
+        const double gq = 0.5 * dLdD * rcp_d(e[j].D);
+        // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
+        const double ux = fma(A, lx, fma(B, ly[j], 0.5 * qd));
+        const double uy = fma(B, lx, fma(Cc, ly[j], 0.5 * qe));
+        const double gux = gq * ux, guy = gq * uy;
+        const double sc = rp.ags_scope ? om : 1.0;
+        if (geo) {
+          gv[0] += -2.0 * gux;
+          gv[1] += -2.0 * guy;
+          gv[2] += -gux * ux;
+          gv[3] += -2.0 * gux * uy;
+          gv[4] += -guy * uy;
+        }
+        if (contrib[j] && !e[j].clamped) gv[5] += (1.0 - e[j].D * rp.inv_lam) * dLda * sc;
+        const double wsc = contrib[j] ? w * sc : 0.0;
+        gv[6] += wsc * G0[j];
+        gv[7] += wsc * G1[j];
+        gv[8] += wsc * G2[j];
+      }
       // wave-wide FP64 sums (all lanes active here), one LDS add per wave
       static_assert(kGrad2d == 9, "eight fields summed together, one alone");
       const double s8 = wave_sum8_d(gv, lane);
@@ -583,7 +621,8 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     dim3 grid((unsigned)p.T);
     ProfScope ps("raster_bwd", s);
 #define LS_BWD(TW_, TH_)                                                                         \
-  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
+  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(bwd_threads<TW_, TH_>()), 0, s, cams, \
+                     p.C, ranges, \
                      p.T, p.K, chunk_base, vals, proj, p.M, batch, rp, final_T, last, dL_dimage, \
                      dL_dalpha, grad2d)
     if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_BWD(16, 16);
