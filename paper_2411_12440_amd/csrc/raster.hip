@@ -229,17 +229,27 @@ __device__ __forceinline__ int stage_batch(Stage<NS, NWB>& st, const uint32_t* _
 // Forward composite of chunk c of K: each tile continues from the state its
 // pixels reached in the previous chunks (T and colour in FP64, the stop flag
 // and `last`) over its segment of this chunk's sorted list.
+// Threads of the raster kernels: a tile of 128 or more pixels gives each lane
+// two vertically adjacent pixels, so one read of the staged entry (and in the
+// backward pass one wave-wide reduction) serves both.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
+constexpr int raster_ppl() { return TW * TH >= 128 ? 2 : 1; }
+template <int TW, int TH>
+constexpr int raster_threads() { return TW * TH / raster_ppl<TW, TH>(); }
+
+template <int TW, int TH>
+__global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_fwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all, int64_t T_all,
     int c, int K, const int64_t* __restrict__ chunk_base, const uint32_t* __restrict__ vals,
     const ProjRec* __restrict__ proj, int64_t M, int batch, RasterParams rp,
     double4* __restrict__ state, uint8_t* __restrict__ done_px, uint32_t* __restrict__ alive,
     float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ last,
     uint32_t* __restrict__ tile_contrib) {
-  constexpr int NT = TW * TH;
-  __shared__ Stage<NT, NT / 64> st;
-  __shared__ uint32_t s_cnt[NT / 64];
+  constexpr int PPL = raster_ppl<TW, TH>();
+  constexpr int NTB = raster_threads<TW, TH>();
+  constexpr int NWB = NTB / 64;
+  __shared__ Stage<NTB, NWB> st;
+  __shared__ uint32_t s_cnt[NWB];
   const int tid = threadIdx.x;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   if (c > 0 && alive[tile] == 0u) return;
@@ -256,61 +266,95 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   const CamInfo& ci = cams[ci_idx];
   const int64_t local = tile - ci.tile_off;
   const int ty = (int)(local / ci.GX), tx = (int)(local % ci.GX);
-  const int lxi = tid % TW, lyi = tid / TW;
-  const int px = tx * TW + lxi, py = ty * TH + lyi;
-  const bool inside = (px < ci.W) && (py < ci.H);
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
-  const double lx = (double)lxi, ly = (double)lyi;
-  const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
+  const int lxi = tid % TW;
+  const int px = tx * TW + lxi;
+  const double lx = (double)lxi;
 
-  double T = 1.0, cr = 0.0, cg = 0.0, cb = 0.0;
-  int32_t lastc = 0;
+  // per pixel of this lane: transmittance and colour (FP64), the stop flag
+  // and `last`, continued from the previous chunks
+  double ly[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
+  int64_t pix[PPL];
+  bool inside[PPL], done[PPL];
+  int32_t lastc[PPL];
   uint32_t ncon = 0;
-  bool done = !inside;
-  if (c > 0 && inside) {
-    const double4 sv = state[pix];
-    T = sv.x;
-    cr = sv.y;
-    cg = sv.z;
-    cb = sv.w;
-    done = done_px[pix] != 0;
-    lastc = last[pix];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int lyi = (tid / TW) * PPL + j;
+    const int py = ty * TH + lyi;
+    ly[j] = (double)lyi;
+    inside[j] = (px < ci.W) && (py < ci.H);
+    pix[j] = ci.pix_off + (int64_t)py * ci.W + px;
+    T[j] = 1.0;
+    cr[j] = cg[j] = cb[j] = 0.0;
+    lastc[j] = 0;
+    done[j] = !inside[j];
+    if (c > 0 && inside[j]) {
+      const double4 sv = state[pix[j]];
+      T[j] = sv.x;
+      cr[j] = sv.y;
+      cg[j] = sv.z;
+      cb[j] = sv.w;
+      done[j] = done_px[pix[j]] != 0;
+      lastc[j] = last[pix[j]];
+    }
   }
-  for (int32_t p0 = 0; p0 < len; p0 += batch) {
-    if (__syncthreads_count(!done) == 0) break;
-    const int nb = (len - p0) < batch ? (len - p0) : batch;
-    const int cnt = stage_batch<TW, TH, NT, NT / 64>(st, vals, proj, M, tid < nb, start + p0 + tid,
-                                        prefix + p0 + tid, x0c, y0c, rp.lam2);
-    if (!done) {
+  auto all_done = [&]() {
+    bool a = true;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) a = a && done[j];
+    return a;
+  };
+  const int bsz = batch < NTB ? batch : NTB;
+  for (int32_t p0 = 0; p0 < len; p0 += bsz) {
+    if (__syncthreads_count(!all_done()) == 0) break;
+    const int nb = (len - p0) < bsz ? (len - p0) : bsz;
+    const int cnt = stage_batch<TW, TH, NTB, NWB>(st, vals, proj, M, tid < nb, start + p0 + tid,
+                                                  prefix + p0 + tid, x0c, y0c, rp.lam2);
+    if (!all_done()) {
       for (int k = 0; k < cnt; ++k) {
-        const double q = quad_local(st.qa[k], st.qb[k], st.qc[k], st.qd[k], st.qe[k], st.qf[k],
-                                    lx, ly);
-        if (!(q < rp.lam2)) continue;
-        const PairEval e = pair_eval(q, (double)st.o[k], rp);
-        if (!(e.alpha > 0.0) || e.alpha < rp.amin) continue;
-        const double Tn = T * e.oma;
-        if (Tn < rp.tmin) {
-          done = true;
-          break;
+        const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
+        const double qd = st.qd[k], qe = st.qe[k], qf = st.qf[k];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          if (done[j]) continue;
+          const double q = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
+          if (!(q < rp.lam2)) continue;
+          const PairEval e = pair_eval(q, (double)st.o[k], rp);
+          if (!(e.alpha > 0.0) || e.alpha < rp.amin) continue;
+          const double Tn = T[j] * e.oma;
+          if (Tn < rp.tmin) {
+            done[j] = true;
+            continue;
+          }
+          const double w = e.alpha * T[j];
+          cr[j] = fma((double)st.r[k], w, cr[j]);
+          cg[j] = fma((double)st.g[k], w, cg[j]);
+          cb[j] = fma((double)st.b[k], w, cb[j]);
+          T[j] = Tn;
+          lastc[j] = st.pos[k] + 1;
+          ++ncon;
         }
-        const double w = e.alpha * T;
-        cr = fma((double)st.r[k], w, cr);
-        cg = fma((double)st.g[k], w, cg);
-        cb = fma((double)st.b[k], w, cb);
-        T = Tn;
-        lastc = st.pos[k] + 1;
-        ++ncon;
+        if (all_done()) break;
       }
     }
   }
-  if (inside) {
-    const int64_t plane = (int64_t)ci.W * ci.H;
-    const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
-    image[ib] = (float)(cr + T * (double)rp.bg0);
-    image[ib + plane] = (float)(cg + T * (double)rp.bg1);
-    image[ib + 2 * plane] = (float)(cb + T * (double)rp.bg2);
-    final_T[pix] = (float)T;
-    last[pix] = lastc;
+  const int64_t plane = (int64_t)ci.W * ci.H;
+  bool live = false;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    if (!inside[j]) continue;
+    const int64_t ib = 3 * ci.pix_off + (pix[j] - ci.pix_off);
+    image[ib] = (float)(cr[j] + T[j] * (double)rp.bg0);
+    image[ib + plane] = (float)(cg[j] + T[j] * (double)rp.bg1);
+    image[ib + 2 * plane] = (float)(cb[j] + T[j] * (double)rp.bg2);
+    final_T[pix[j]] = (float)T[j];
+    last[pix[j]] = lastc[j];
+    if (K > 1 && c < K - 1) {
+      state[pix[j]] = make_double4(T[j], cr[j], cg[j], cb[j]);
+      done_px[pix[j]] = done[j] ? 1 : 0;
+      live = live || !done[j];
+    }
   }
   // contributing pairs of the tile (a statistic for throughput accounting)
   for (int d = 32; d > 0; d >>= 1) ncon += __shfl_xor(ncon, d, 64);
@@ -319,37 +363,25 @@ __global__ __launch_bounds__(TW* TH) void raster_fwd_kernel(
   if (tid == 0) {
     uint32_t t = 0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) t += s_cnt[w];
+    for (int w = 0; w < NWB; ++w) t += s_cnt[w];
     tile_contrib[tile] = (c > 0 ? tile_contrib[tile] : 0u) + t;
   }
   if (K > 1 && c < K - 1) {
-    if (inside) {
-      state[pix] = make_double4(T, cr, cg, cb);
-      done_px[pix] = done ? 1 : 0;
-    }
-    const int any_live = __syncthreads_or(inside && !done);
+    const int any_live = __syncthreads_or(live);
     if (tid == 0) alive[tile] = any_live ? 1u : 0u;
   }
 }
 
-// Backward threads: a tile of 128 or more pixels gives each lane two
-// vertically adjacent pixels, so one wave-wide reduction and one read of the
-// staged entry serve both.
 template <int TW, int TH>
-constexpr int bwd_ppl() { return TW * TH >= 128 ? 2 : 1; }
-template <int TW, int TH>
-constexpr int bwd_threads() { return TW * TH / bwd_ppl<TW, TH>(); }
-
-template <int TW, int TH>
-__global__ __launch_bounds__((bwd_threads<TW, TH>())) void raster_bwd_kernel(
+__global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all,
     int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
     RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
     double* __restrict__ grad2d) {
-  constexpr int PPL = bwd_ppl<TW, TH>();
-  constexpr int NTB = bwd_threads<TW, TH>();
+  constexpr int PPL = raster_ppl<TW, TH>();
+  constexpr int NTB = raster_threads<TW, TH>();
   constexpr int NWB = NTB / 64;
   // at most 128 entries per batch, so that the FP64 accumulators fit beside
   // the staged entries without lowering the occupancy
@@ -586,7 +618,8 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
     if (p.K > 1 && (e = launch_chunk_bin(p, c, ws, s))) return e;
     ProfScope ps("raster_fwd", s);
 #define LS_FWD(TW_, TH_)                                                                           \
-  hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_>), grid, dim3(TW_ * TH_), 0, s, cams, p.C, ranges, \
+  hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_>), grid, dim3(raster_threads<TW_, TH_>()), 0, s,   \
+                     cams, p.C, ranges, \
                      p.T, c, p.K, chunk_base, vals, proj, p.M, batch, rp, state, done, alive, image, \
                      final_T, last, tile_contrib)
     if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_FWD(16, 16);
@@ -621,7 +654,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     dim3 grid((unsigned)p.T);
     ProfScope ps("raster_bwd", s);
 #define LS_BWD(TW_, TH_)                                                                         \
-  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(bwd_threads<TW_, TH_>()), 0, s, cams, \
+  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(raster_threads<TW_, TH_>()), 0, s, cams, \
                      p.C, ranges, \
                      p.T, p.K, chunk_base, vals, proj, p.M, batch, rp, final_T, last, dL_dimage, \
                      dL_dalpha, grad2d)
