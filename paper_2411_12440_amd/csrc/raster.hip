@@ -73,19 +73,17 @@ __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterPa
   return e;
 }
 
-// e^-x for x >= 0 in FP64: x = k ln2 + r with |r| <= ln2 / 2 (ln2 split in a
-// high part whose products with k are exact and a low part), e^-r from its
-// Taylor series to degree 11 (truncation below 6e-15), scaled by 2^-k.
+// e^-x for x >= 0 in FP64: x = k ln2/2 + r with |r| <= ln2 / 4 (ln2/2 split
+// in a high part whose products with k are exact and a low part), e^-r from
+// its Taylor series to degree 8 (truncation below 1e-13), scaled by
+// 2^-(k/2) (with 1/sqrt 2 for odd k).
 __device__ __forceinline__ double exp_neg(double x) {
-  if (!(x < 708.0)) return 0.0;
-  const double k = rint(x * 1.4426950408889634);
-  double r = fma(-k, 6.93147180369123816490e-01, x);
-  r = fma(-k, 1.90821492927058770002e-10, r);
+  x = fmin(x, 708.0);   // below 1e-307 the weight is as good as 0
+  const double k = rint(x * 2.8853900817779268);          // 2 / ln 2
+  double r = fma(-k, 3.46573590184561908245e-01, x);      // ln2 / 2, high part
+  r = fma(-k, 9.54107464635293850010e-11, r);             // low part
   const double t = -r;
-  double p = 1.0 / 39916800.0;
-  p = fma(p, t, 1.0 / 3628800.0);
-  p = fma(p, t, 1.0 / 362880.0);
-  p = fma(p, t, 1.0 / 40320.0);
+  double p = 1.0 / 40320.0;
   p = fma(p, t, 1.0 / 5040.0);
   p = fma(p, t, 1.0 / 720.0);
   p = fma(p, t, 1.0 / 120.0);
@@ -94,7 +92,9 @@ __device__ __forceinline__ double exp_neg(double x) {
   p = fma(p, t, 0.5);
   p = fma(p, t, 1.0);
   p = fma(p, t, 1.0);
-  return ldexp(p, -(int)k);
+  const int ki = (int)k;
+  if (ki & 1) p *= 0.70710678118654752440;
+  return ldexp(p, -(ki >> 1));
 }
 
 // 1/x in FP64 from the hardware estimate and two Newton steps (for normal,
@@ -509,12 +509,10 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
         const double GdC = G0[j] * cr + G1[j] * cg + G2[j] * cb;
         const double GdS = G0[j] * S0[j] + G1[j] * S1[j] + G2[j] * S2[j] + GSa[j];
         const double dLda = Ti * GdC - GdS * inv;
-        if (contrib[j]) {
-          S0[j] = fma(cr, w, S0[j]);
-          S1[j] = fma(cg, w, S1[j]);
-          S2[j] = fma(cb, w, S2[j]);
-          T[j] = Ti;
-        }
+        S0[j] = contrib[j] ? fma(cr, w, S0[j]) : S0[j];
+        S1[j] = contrib[j] ? fma(cg, w, S1[j]) : S1[j];
+        S2[j] = contrib[j] ? fma(cb, w, S2[j]) : S2[j];
+        T[j] = contrib[j] ? Ti : T[j];
         double om = 1.0;
         if (rp.ags) om = exp_neg(rp.ags_arg ? qq[j] * rp.inv_lam2 : qq[j]);
         // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
@@ -530,14 +528,12 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
         const double uy = fma(B, lx, fma(Cc, ly[j], 0.5 * qe));
         const double gux = gq * ux, guy = gq * uy;
         const double sc = rp.ags_scope ? om : 1.0;
-        if (geo) {
-          gv[0] += -2.0 * gux;
-          gv[1] += -2.0 * guy;
-          gv[2] += -gux * ux;
-          gv[3] += -2.0 * gux * uy;
-          gv[4] += -guy * uy;
-        }
-        if (contrib[j] && !e[j].clamped) gv[5] += (1.0 - e[j].D * rp.inv_lam) * dLda * sc;
+        gv[0] += geo ? -2.0 * gux : 0.0;
+        gv[1] += geo ? -2.0 * guy : 0.0;
+        gv[2] += geo ? -gux * ux : 0.0;
+        gv[3] += geo ? -2.0 * gux * uy : 0.0;
+        gv[4] += geo ? -guy * uy : 0.0;
+        gv[5] += (contrib[j] && !e[j].clamped) ? (1.0 - e[j].D * rp.inv_lam) * dLda * sc : 0.0;
         const double wsc = contrib[j] ? w * sc : 0.0;
         gv[6] += wsc * G0[j];
         gv[7] += wsc * G1[j];
