@@ -43,6 +43,7 @@ struct RasterParams {
 // kernels take every skip/stop decision identically.
 struct PairEval {
   double D, alpha, oma;
+  double invD;   // 1 / D (meaningful only for D > 0; the forward pass ignores it)
   bool clamped;
 };
 
@@ -51,9 +52,12 @@ struct PairEval {
 // reciprocal square root as a start and one FP64 Newton step, which brings
 // the relative error from about 2^-22 to below 1e-13.  Below 1e-30 the result
 // is 0 (an absolute error under 1e-15).
-__device__ __forceinline__ double sqrt_nonneg(double q) {
-  if (!(q > 1e-30)) return 0.0;
+// The same start gives 1/sqrt(q) with one Newton step for the reciprocal
+// square root.
+__device__ __forceinline__ double sqrt_nonneg(double q, double* inv) {
   const double y = (double)__builtin_amdgcn_rsqf((float)q);
+  *inv = y * fma(-0.5 * q, y * y, 1.5);
+  if (!(q > 1e-30)) return 0.0;
   const double d0 = q * y;
   return fma(0.5 * y, fma(-d0, d0, q), d0);
 }
@@ -61,7 +65,7 @@ __device__ __forceinline__ double sqrt_nonneg(double q) {
 __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterParams& rp) {
 #pragma clang fp contract(off)
   PairEval e;
-  e.D = sqrt_nonneg(q);
+  e.D = sqrt_nonneg(q, &e.invD);
   const double t = o * (e.D * rp.inv_lam);
   e.alpha = o - t;
   e.oma = (1.0 - o) + t;
@@ -522,7 +526,7 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
         // would amplify the sum's rounding for elongated splats.
         const bool geo = contrib[j] && !e[j].clamped && e[j].D > 0.0;
         const double dLdD = -(o * dLda) * rp.inv_lam * om;
-        const double gq = 0.5 * dLdD * rcp_d(e[j].D);
+        const double gq = 0.5 * dLdD * e[j].invD;
         // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
         const double ux = fma(A, lx, fma(B, ly[j], 0.5 * qd));
         const double uy = fma(B, lx, fma(Cc, ly[j], 0.5 * qe));
