@@ -36,6 +36,8 @@ struct RasterParams {
   double amin, amax, oma_max, tmin;
   float bg0, bg1, bg2;
   int ags, ags_arg, ags_scope;
+  int exp_tab;        // the AGS weight of every contributing pair can use exp_neg_tab
+  double ags_scale;   // AGS exponent per unit D'^2: 1 / lambda^2 or 1
 };
 
 // alpha and 1 - alpha of one (pixel, splat) pair, in FP64.  Shared by the
@@ -99,6 +101,28 @@ __device__ __forceinline__ double exp_neg(double x) {
   const int ki = (int)k;
   if (ki & 1) p *= 0.70710678118654752440;
   return ldexp(p, -(ki >> 1));
+}
+
+// e^-x on [0, kExpTabN / kExpTabStep) from a table of e^-(j / kExpTabStep)
+// (built with exp_neg) and the Taylor series of e^-r for the remainder
+// 0 <= r < 1 / kExpTabStep to degree 7 (truncation below 6e-15).  Arguments
+// outside the range are clamped into it, so the table read stays in bounds;
+// callers use it only where every argument that matters lies inside.
+constexpr int kExpTabStep = 16;
+constexpr int kExpTabN = 128;
+__device__ __forceinline__ double exp_neg_tab(double x, const double* tab) {
+  x = fmin(fmax(x, 0.0), (double)kExpTabN / kExpTabStep - 0.01);   // NaN -> 0
+  const int j = (int)(x * (double)kExpTabStep);
+  const double t = fma((double)j, -1.0 / kExpTabStep, x) * -1.0;   // -r, exact
+  double p = 1.0 / 5040.0;
+  p = fma(p, t, 1.0 / 720.0);
+  p = fma(p, t, 1.0 / 120.0);
+  p = fma(p, t, 1.0 / 24.0);
+  p = fma(p, t, 1.0 / 6.0);
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  return tab[j] * p;
 }
 
 // 1/x in FP64 from the hardware estimate and two Newton steps (for normal,
@@ -395,7 +419,10 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   __shared__ int32_t s_max[NWB];
   __shared__ int64_t s_segbase[kMaxDepthChunks];
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
+  __shared__ double s_exptab[kExpTabN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (rp.ags && rp.exp_tab)
+    for (int i = tid; i < kExpTabN; i += NTB) s_exptab[i] = exp_neg((double)i / kExpTabStep);
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int c = cam_of_tile(cams, C, tile);
   const CamInfo& ci = cams[c];
@@ -417,10 +444,11 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   const int64_t len = s_segpre[K];
 
   // per pixel of this lane: position, upstream gradients, transmittance and
-  // the suffix colour behind the current splat (from the background term)
+  // the upstream gradient's dot product with the suffix colour behind the
+  // current splat
   const int lxi = tid % TW;
   double lx = (double)lxi, ly[PPL];
-  double T[PPL], G0[PPL], G1[PPL], G2[PPL], GSa[PPL], S0[PPL], S1[PPL], S2[PPL];
+  double T[PPL], G0[PPL], G1[PPL], G2[PPL], GS[PPL];
   int32_t mylast[PPL];
   int32_t mx = 0;
 #pragma unroll
@@ -444,12 +472,10 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
       G2[j] = dL_dimage[ib + 2 * plane];
       if (dL_dalpha) GA = dL_dalpha[pix];
     }
-    S0[j] = T[j] * (double)rp.bg0;
-    S1[j] = T[j] * (double)rp.bg1;
-    S2[j] = T[j] * (double)rp.bg2;
-    // the accumulated opacity 1 - T_final as a fourth channel: splat colours
-    // 0, background -1, so its suffix term is the constant -T_final
-    GSa[j] = -GA * T[j];
+    // G . S for the suffix colour S behind the current splat, which starts
+    // as the background term T_final bg; the accumulated opacity
+    // 1 - T_final is a fourth channel with splat colour 0 and background -1
+    GS[j] = T[j] * (G0[j] * (double)rp.bg0 + G1[j] * (double)rp.bg1 + G2[j] * (double)rp.bg2 - GA);
     mx = mylast[j] > mx ? mylast[j] : mx;
   }
   // tile-wide maximum of `last`
@@ -462,6 +488,8 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   int32_t maxlast = 0;
 #pragma unroll
   for (int w = 0; w < NWB; ++w) maxlast = s_max[w] > maxlast ? s_max[w] : maxlast;
+  const int32_t wave_last = mx;   // entries at or beyond it concern no pixel of this wave
+  static_assert(NS <= 128, "two staged entries per lane when trimming a batch");
 
   const int bsz = batch < NS ? batch : NS;
   for (int32_t hi = maxlast; hi > 0; hi -= bsz) {
@@ -478,7 +506,15 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
         stage_batch<TW, TH, NS, NWB>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.lam2);
     for (int i = tid; i < kGrad2d * NS; i += NTB) (&s_acc[0][0])[i] = 0.0;
     __syncthreads();
-    for (int k = cnt - 1; k >= 0; --k) {
+    // the staged positions increase with k: the entries this wave needs are
+    // the first kend, those before its last contributor
+    int kend;
+    {
+      const bool b0 = lane < cnt && st.pos[lane] < wave_last;
+      const bool b1 = lane + 64 < cnt && st.pos[lane + 64] < wave_last;
+      kend = __popcll(__builtin_amdgcn_ballot_w64(b0)) + __popcll(__builtin_amdgcn_ballot_w64(b1));
+    }
+    for (int k = kend - 1; k >= 0; --k) {
       // Evaluated for every lane and masked at the end, so that the wave
       // runs one path; a wave with no contributing pixel skips the entry.
       const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
@@ -500,44 +536,50 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
       if (__builtin_amdgcn_ballot_w64(any) == 0ull) continue;
       const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
       const double A = qa, B = 0.5 * qb, Cc = qc;
+      const double nol = -0.5 * o * rp.inv_lam;
       double gv[kGrad2d];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.0;
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
-        // transmittance, suffix colour and dL/dalpha (they carry the error
-        // of every step), the per-pair terms and their sums: all FP64
+        // transmittance, G . suffix colour and dL/dalpha (they carry the
+        // error of every step), the per-pair terms and their sums: all FP64.
+        // dL/dalpha = (T G.c - G.S) / (1 - alpha) with T the transmittance
+        // behind the splat; G.S then takes the splat's share w G.c.
         const double inv = rcp_d(e[j].oma);
         const double Ti = T[j] * inv;
         const double w = e[j].alpha * Ti;
         const double GdC = G0[j] * cr + G1[j] * cg + G2[j] * cb;
-        const double GdS = G0[j] * S0[j] + G1[j] * S1[j] + G2[j] * S2[j] + GSa[j];
-        const double dLda = Ti * GdC - GdS * inv;
-        S0[j] = contrib[j] ? fma(cr, w, S0[j]) : S0[j];
-        S1[j] = contrib[j] ? fma(cg, w, S1[j]) : S1[j];
-        S2[j] = contrib[j] ? fma(cb, w, S2[j]) : S2[j];
+        const double dLda = fma(T[j], GdC, -GS[j]) * inv;
+        GS[j] = contrib[j] ? fma(w, GdC, GS[j]) : GS[j];
         T[j] = contrib[j] ? Ti : T[j];
         double om = 1.0;
-        if (rp.ags) om = exp_neg(rp.ags_arg ? qq[j] * rp.inv_lam2 : qq[j]);
+        if (rp.ags) {
+          const double xa = qq[j] * rp.ags_scale;
+          om = rp.exp_tab ? exp_neg_tab(xa, s_exptab) : exp_neg(xa);
+        }
         // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
         // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the
         // conic) is what the projection backward differentiates, so its
         // gradient is summed here; going through the inverse after the sum
         // would amplify the sum's rounding for elongated splats.
+        // The masks act on the per-pair factors (gq, the opacity factor and
+        // w), so that a masked pair adds exact zeros to the sums.
         const bool geo = contrib[j] && !e[j].clamped && e[j].D > 0.0;
-        const double dLdD = -(o * dLda) * rp.inv_lam * om;
-        const double gq = 0.5 * dLdD * e[j].invD;
+        // dL/dq = dL/dalpha (-o / lambda) omega / (2 D)
+        const double gq = geo ? nol * dLda * om * e[j].invD : 0.0;
         // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
         const double ux = fma(A, lx, fma(B, ly[j], 0.5 * qd));
         const double uy = fma(B, lx, fma(Cc, ly[j], 0.5 * qe));
         const double gux = gq * ux, guy = gq * uy;
         const double sc = rp.ags_scope ? om : 1.0;
-        gv[0] += geo ? -2.0 * gux : 0.0;
-        gv[1] += geo ? -2.0 * guy : 0.0;
-        gv[2] += geo ? -gux * ux : 0.0;
-        gv[3] += geo ? -2.0 * gux * uy : 0.0;
-        gv[4] += geo ? -guy * uy : 0.0;
-        gv[5] += (contrib[j] && !e[j].clamped) ? (1.0 - e[j].D * rp.inv_lam) * dLda * sc : 0.0;
+        gv[0] = fma(-2.0, gux, gv[0]);
+        gv[1] = fma(-2.0, guy, gv[1]);
+        gv[2] = fma(-gux, ux, gv[2]);
+        gv[3] = fma(-2.0 * gux, uy, gv[3]);
+        gv[4] = fma(-guy, uy, gv[4]);
+        const double go = (contrib[j] && !e[j].clamped) ? dLda * sc : 0.0;
+        gv[5] = fma(1.0 - e[j].D * rp.inv_lam, go, gv[5]);
         const double wsc = contrib[j] ? w * sc : 0.0;
         gv[6] += wsc * G0[j];
         gv[7] += wsc * G1[j];
@@ -545,10 +587,14 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
       }
       // wave-wide FP64 sums (all lanes active here), one LDS add per wave
       static_assert(kGrad2d == 9, "eight fields summed together, one alone");
+      // lanes 8g hold fields 0..7 and lane 63 field 8: one LDS add at
+      // lane-dependent addresses
       const double s8 = wave_sum8_d(gv, lane);
-      if ((lane & 7) == 0 && s8 != 0.0) atomicAdd(&s_acc[k][wave_sum8_field(lane >> 3)], s8);
       const double s1 = wave_sum_to_lane63_d(gv[8]);
-      if (lane == 63 && s1 != 0.0) atomicAdd(&s_acc[k][8], s1);
+      const bool top = lane == 63;
+      const double sv = top ? s1 : s8;
+      if (((lane & 7) == 0 || top) && sv != 0.0)
+        atomicAdd(&s_acc[k][top ? 8 : wave_sum8_field(lane >> 3)], sv);
     }
     __syncthreads();
     if (tid < cnt) {
@@ -582,6 +628,10 @@ RasterParams make_params(const ls_config* cfg) {
   rp.ags = cfg->ags;
   rp.ags_arg = cfg->ags_arg;
   rp.ags_scope = cfg->ags_scope;
+  // largest AGS exponent of a contributing pair (q < lambda^2)
+  const double xmax = cfg->ags_arg ? 1.0 : rp.lam2;
+  rp.exp_tab = xmax < (double)kExpTabN / kExpTabStep - 0.01;
+  rp.ags_scale = cfg->ags_arg ? rp.inv_lam2 : 1.0;
   return rp;
 }
 

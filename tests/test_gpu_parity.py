@@ -65,18 +65,22 @@ def test_ragged_tile_shapes(tw, th, batch):
     compare_forward(g, fw, cams)
 
 
-@pytest.mark.parametrize("ags,ags_arg,ags_scope,strict,chunks",
-                         [(False, 0, 0, False, 1), (True, 0, 0, False, 1), (True, 1, 0, True, 1),
-                          (True, 0, 1, False, 1), (False, 0, 0, True, 1), (True, 0, 0, False, 6),
-                          (False, 0, 0, True, 4)])
-def test_forward_backward_small(ags, ags_arg, ags_scope, strict, chunks):
+# lambda 3 puts the AGS exponent beyond the range of the tabulated
+# exponential, so the backward pass takes its series path there
+@pytest.mark.parametrize("ags,ags_arg,ags_scope,strict,chunks,lam",
+                         [(False, 0, 0, False, 1, 2.5), (True, 0, 0, False, 1, 2.5),
+                          (True, 1, 0, True, 1, 2.5), (True, 0, 1, False, 1, 2.5),
+                          (False, 0, 0, True, 1, 2.5), (True, 0, 0, False, 6, 2.5),
+                          (False, 0, 0, True, 4, 2.5), (True, 0, 1, False, 3, 3.0),
+                          (True, 0, 0, False, 1, 2.0)])
+def test_forward_backward_small(ags, ags_arg, ags_scope, strict, chunks, lam):
     say(f"case: fwd+bwd 3000 splats SH3 200x120 ags={ags} arg={ags_arg} scope={ags_scope} "
-        f"strict={strict} chunks={chunks}")
+        f"strict={strict} chunks={chunks} lambda={lam}")
     scene = scenes.make_scene(3000, 77, -3.0, 0.5, 3)
     cams = scenes.front_camera(200, 120)
     off = np.array([0, scene.n])
     ocfg, gkw = cfg_pair(ags=ags, ags_arg=ags_arg, ags_scope=ags_scope, strict=strict,
-                         bg=(0.1, 0.2, 0.3), depth_chunks=chunks)
+                         bg=(0.1, 0.2, 0.3), depth_chunks=chunks, lambda_=lam)
     G = scenes.upstream_grad(cams, 7002)
     fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
     # zero the upstream gradient where a decision sits on a threshold
