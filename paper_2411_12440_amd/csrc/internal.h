@@ -170,6 +170,24 @@ __device__ __forceinline__ double swap16_add_d(double a, double b) {
   return a2 + b2;
 }
 
+// 1/x in FP64 from the hardware estimate and two Newton steps (for normal,
+// nonzero x the result is within an ulp or two of the rounded quotient).
+__device__ __forceinline__ double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// 1/sqrt(x) in FP64 for normal x > 0: the hardware estimate and two Newton
+// steps for the reciprocal square root.
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  return y * fma(-0.5 * x, y * y, 1.5);
+}
+
 // wave_sum8 in FP64: lane 8g receives the sum of v[wave_sum8_field(g)].
 __device__ __forceinline__ double wave_sum8_d(const double* v, int lane) {
   const double a = swap32_add_d(v[0], v[1]), b = swap32_add_d(v[2], v[3]);

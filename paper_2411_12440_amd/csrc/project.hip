@@ -68,11 +68,14 @@ struct BinOut {
   uint32_t dkey;
 };
 
-__device__ __noinline__ BinOut bin_fp32(float mx_, float my_, float mz_, float s0, float s1,
-                                         float s2, float qw, float qx, float qy, float qz,
-                                         const float* V, const float* in4, float Wf, float Hf,
-                                         float lam, float eps, float clip, float near_z,
-                                         float far_z, int TW, int TH) {
+// The splat's 3D covariance in the FP32 sequence (it does not depend on the
+// camera, so a splat computes it once for all its cameras).
+struct CovF {
+  float S[3][3];
+};
+
+__device__ __forceinline__ CovF bin_cov_fp32(float s0, float s1, float s2, float qw, float qx,
+                                             float qy, float qz) {
 #pragma clang fp contract(off)
   float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
   float r = sqrtf(n2);
@@ -91,10 +94,19 @@ __device__ __noinline__ BinOut bin_fp32(float mx_, float my_, float mz_, float s
   float M[3][3];
   for (int rr = 0; rr < 3; ++rr)
     for (int cc = 0; cc < 3; ++cc) M[rr][cc] = R[rr][cc] * s[cc];
-  float Sg[3][3];
+  CovF cv;
   for (int rr = 0; rr < 3; ++rr)
     for (int cc = 0; cc < 3; ++cc)
-      Sg[rr][cc] = (M[rr][0] * M[cc][0] + M[rr][1] * M[cc][1]) + M[rr][2] * M[cc][2];
+      cv.S[rr][cc] = (M[rr][0] * M[cc][0] + M[rr][1] * M[cc][1]) + M[rr][2] * M[cc][2];
+  return cv;
+}
+
+__device__ __noinline__ BinOut bin_fp32(float mx_, float my_, float mz_, const CovF& cv,
+                                         const float* V, const float* in4, float Wf, float Hf,
+                                         float lam, float eps, float clip, float near_z,
+                                         float far_z, int TW, int TH) {
+#pragma clang fp contract(off)
+  const float (*Sg)[3] = cv.S;
   float t0 = ((V[0] * mx_ + V[1] * my_) + V[2] * mz_) + V[3];
   float t1 = ((V[4] * mx_ + V[5] * my_) + V[6] * mz_) + V[7];
   float t2 = ((V[8] * mx_ + V[9] * my_) + V[10] * mz_) + V[11];
@@ -256,12 +268,14 @@ struct Geo {
   double mx, my;
 };
 
-__device__ __forceinline__ void geo_compute(const CamInfo& ci, double mux, double muy, double muz,
-                                            double s0, double s1, double s2, double qw, double qx,
-                                            double qy, double qz, double clip, double eps, Geo& g) {
+// The camera-independent part: normalised quaternion, rotation, R diag(s)
+// and the 3D covariance.
+__device__ __forceinline__ void geo_splat(double s0, double s1, double s2, double qw, double qx,
+                                          double qy, double qz, Geo& g) {
   double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   g.qn = qn;
-  double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+  const double iqn = rcp_d(qn);
+  double w = qw * iqn, x = qx * iqn, y = qy * iqn, z = qz * iqn;
   g.q[0] = w; g.q[1] = x; g.q[2] = y; g.q[3] = z;
   double* R = g.R;
   R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
@@ -276,18 +290,25 @@ __device__ __forceinline__ void geo_compute(const CamInfo& ci, double mux, doubl
   };
   g.S[0] = dot3(0, 0); g.S[1] = dot3(0, 1); g.S[2] = dot3(0, 2);
   g.S[3] = dot3(1, 1); g.S[4] = dot3(1, 2); g.S[5] = dot3(2, 2);
+}
+
+// The camera's part (needs g.S from geo_splat): camera-space centre,
+// projection, clipped Jacobian, dilated 2D covariance and its conic.
+__device__ __forceinline__ void geo_cam(const CamInfo& ci, double mux, double muy, double muz,
+                                        double clip, double eps, Geo& g) {
   const double* Wr = ci.R;
   for (int r = 0; r < 3; ++r)
     g.t[r] = Wr[3 * r] * mux + Wr[3 * r + 1] * muy + Wr[3 * r + 2] * muz + ci.t[r];
   double tx = g.t[0], ty = g.t[1], tz = g.t[2];
-  g.mx = ci.fx * tx / tz + ci.cx;
-  g.my = ci.fy * ty / tz + ci.cy;
-  double limx = clip * 0.5 * (double)ci.W / ci.fx;
-  double limy = clip * 0.5 * (double)ci.H / ci.fy;
-  g.u = tx / tz; g.v = ty / tz;
+  const double iz = rcp_d(tz);
+  g.mx = ci.fx * tx * iz + ci.cx;
+  g.my = ci.fy * ty * iz + ci.cy;
+  double limx = clip * 0.5 * (double)ci.W * rcp_d(ci.fx);
+  double limy = clip * 0.5 * (double)ci.H * rcp_d(ci.fy);
+  g.u = tx * iz; g.v = ty * iz;
   g.uc = fmin(limx, fmax(-limx, g.u));
   g.vc = fmin(limy, fmax(-limy, g.v));
-  double J00 = ci.fx / tz, J02 = -ci.fx * g.uc / tz, J11 = ci.fy / tz, J12 = -ci.fy * g.vc / tz;
+  double J00 = ci.fx * iz, J02 = -ci.fx * g.uc * iz, J11 = ci.fy * iz, J12 = -ci.fy * g.vc * iz;
   for (int c = 0; c < 3; ++c) {
     g.T[c] = J00 * Wr[c] + J02 * Wr[6 + c];
     g.T[3 + c] = J11 * Wr[3 + c] + J12 * Wr[6 + c];
@@ -303,7 +324,15 @@ __device__ __forceinline__ void geo_compute(const CamInfo& ci, double mux, doubl
   g.b = P0[0] * T[3] + P0[1] * T[4] + P0[2] * T[5];
   g.c = P1[0] * T[3] + P1[1] * T[4] + P1[2] * T[5] + eps;
   double det = g.a * g.c - g.b * g.b;
-  g.A = g.c / det; g.B = -g.b / det; g.C = g.a / det;
+  const double idet = rcp_d(det);
+  g.A = g.c * idet; g.B = -g.b * idet; g.C = g.a * idet;
+}
+
+__device__ __forceinline__ void geo_compute(const CamInfo& ci, double mux, double muy, double muz,
+                                            double s0, double s1, double s2, double qw, double qx,
+                                            double qy, double qz, double clip, double eps, Geo& g) {
+  geo_splat(s0, s1, s2, qw, qx, qy, qz, g);
+  geo_cam(ci, mux, muy, muz, clip, eps, g);
 }
 
 template <int DEG>
@@ -326,22 +355,25 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(
   float shc[K * 3];
 #pragma unroll
   for (int k = 0; k < K * 3; ++k) shc[k] = sh[(int64_t)k * N + i];
+  // the 3D covariance, FP32 (binning) and FP64 (geometry), once per splat
+  const CovF cv = bin_cov_fp32(s[0], s[1], s[2], q[0], q[1], q[2], q[3]);
+  Geo g;
+  geo_splat(s[0], s[1], s[2], q[0], q[1], q[2], q[3], g);
 
   for (int c = 0; c < C; ++c) {
     const CamInfo& ci = cams[c];
     if (i < ci.splat_lo || i >= ci.splat_hi) continue;
     int64_t m = ci.pair_off + (i - ci.splat_lo);
-    BinOut bo = bin_fp32(mu[0], mu[1], mu[2], s[0], s[1], s[2], q[0], q[1], q[2], q[3], ci.vm32,
-                         ci.in32, (float)ci.W, (float)ci.H, lam, eps, clip, near_z, far_z, TW, TH);
+    BinOut bo = bin_fp32(mu[0], mu[1], mu[2], cv, ci.vm32, ci.in32, (float)ci.W, (float)ci.H, lam,
+                         eps, clip, near_z, far_z, TW, TH);
     rect[m] = bo.rect;
     ntiles[m] = bo.ntiles;
     dkey[m] = bo.dkey;
     if (bo.ntiles == 0) continue;
-    Geo g;
-    geo_compute(ci, mu[0], mu[1], mu[2], s[0], s[1], s[2], q[0], q[1], q[2], q[3], clip, eps, g);
+    geo_cam(ci, mu[0], mu[1], mu[2], clip, eps, g);
     // colour: SH at the unit direction from the camera centre to the splat
     double vx = mu[0] - ci.campos[0], vy = mu[1] - ci.campos[1], vz = mu[2] - ci.campos[2];
-    double inv = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
+    double inv = rsqrt_d(vx * vx + vy * vy + vz * vz);
     double Y[16];
     sh_eval(DEG, vx * inv, vy * inv, vz * inv, Y);
     double col[3] = {0.5, 0.5, 0.5};
@@ -432,7 +464,7 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_kernel(
     double gJ12 = gT[3] * Wr[6] + gT[4] * Wr[7] + gT[5] * Wr[8];
     double tx = g.t[0], ty = g.t[1], tz = g.t[2];
     double fx = ci.fx, fy = ci.fy;
-    double iz = 1.0 / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+    double iz = rcp_d(tz), iz2 = iz * iz, iz3 = iz2 * iz;
     double gt[3] = {0, 0, 0};
     gt[2] += gJ00 * (-fx * iz2) + gJ11 * (-fy * iz2);
     double limx = clip * 0.5 * (double)ci.W / fx;
@@ -513,7 +545,7 @@ __global__ __launch_bounds__(kProjThreads) void project_bwd_sh_kernel(
     const double gr = grad2d[6 * M + m], gg = grad2d[7 * M + m], gb = grad2d[8 * M + m];
     if (gr == 0.0 && gg == 0.0 && gb == 0.0) continue;
     double vx = mu0 - ci.campos[0], vy = mu1 - ci.campos[1], vz = mu2 - ci.campos[2];
-    double inv = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
+    double inv = rsqrt_d(vx * vx + vy * vy + vz * vz);
     double dx = vx * inv, dy = vy * inv, dz = vz * inv;
     double raw[3];
     sh_raw<DEG>(dx, dy, dz, shc, raw);

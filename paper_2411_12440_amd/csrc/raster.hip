@@ -125,15 +125,6 @@ __device__ __forceinline__ double exp_neg_tab(double x, const double* tab) {
   return tab[j] * p;
 }
 
-// 1/x in FP64 from the hardware estimate and two Newton steps (for normal,
-// positive x the result is within an ulp or two of the rounded quotient).
-__device__ __forceinline__ double rcp_d(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   const int64_t x = b & 7, k = b >> 3;
