@@ -11,12 +11,15 @@ operations are exactly that.
 
 The support of the linear kernel with distribution alignment (Eq. 12) is the
 ellipse D' < lambda; its axis-aligned bounding box has half-extents
-lambda*sqrt(Sigma_2D,xx) and lambda*sqrt(Sigma_2D,yy).  A pixel (px, py) is
+lambda*sqrt(Sigma_2D,xx) and lambda*sqrt(Sigma_2D,yy).  Another kernel of the
+family uses its extent lambda * s_f (config.py) in place of lambda.  A pixel (px, py) is
 sampled at its centre (px + 0.5, py + 0.5).
 """
 from __future__ import annotations
 
 import numpy as np
+
+from .config import extent
 
 f32 = np.float32
 
@@ -36,7 +39,7 @@ def binning_fp32(means, scales, quats, viewmat, intrin, width, height, cfg):
         V = np.asarray(viewmat, f32)
         fx, fy, cx, cy = (f32(v) for v in np.asarray(intrin, f32))
         W, H = f32(width), f32(height)
-        lam, eps, clip = f32(cfg.lambda_), f32(cfg.eps2d), f32(cfg.clip)
+        lam, eps, clip = f32(extent(cfg)), f32(cfg.eps2d), f32(cfg.clip)
         near, far = f32(cfg.near), f32(cfg.far)
 
         # normalised quaternion

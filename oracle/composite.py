@@ -1,9 +1,11 @@
-"""Front-to-back compositing with the linear kernel, and its reverse pass.
+"""Front-to-back compositing with the linear kernel (or another kernel of the
+family in the appendix), and its reverse pass.
 
 For a pixel centre x and a splat with projected centre mu', inverse 2D
 covariance ("conic") and opacity o:
   D'  = sqrt((x - mu')^T Sigma_2D^-1 (x - mu'))            Eq. 11
   L'  = max(0, 1 - D'/lambda)                               Eq. 10 with DA, Eq. 12
+        (another kernel: f(D'/lambda), cut at D' = extent, config.py)
   alpha = min(alpha_max, o * L')                            Eq. 6 (alpha = o * kernel)
   C(x) = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j)         Eq. 6
 The splats are taken in the order of the pixel's tile list (binning.py).
@@ -20,6 +22,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from .config import extent
+
 CHUNK = 512
 FLAG_REL = 1e-4
 
@@ -32,14 +36,60 @@ def _tile_pixels(tx, ty, width, height, cfg):
     return px.ravel(), py.ravel()
 
 
+def kernel_value(q, cfg):
+    """f(D'/lambda) of the configured kernel at q = D'^2 (a negative q, from
+    rounding at a splat's centre, counts as 0), zero from the support cut
+    q >= extent^2 on.  Returns (D', f)."""
+    q = np.maximum(np.asarray(q, np.float64), 0.0)
+    D = np.sqrt(q)
+    lam = cfg.lambda_
+    x = D / lam
+    k = cfg.kernel
+    if k == "linear":
+        f = 1.0 - x
+    elif k == "gaussian":
+        f = np.exp(-q / (2.0 * lam * lam))
+    elif k == "laplacian":
+        f = np.exp(-x)
+    elif k == "cosine":
+        f = 0.5 * (1.0 + np.cos(np.pi * np.minimum(x, 1.0)))
+    else:   # quadratic
+        f = 1.0 - q / (lam * lam)
+    e = extent(cfg)
+    f = np.where(q < e * e, np.maximum(f, 0.0), 0.0)
+    return D, f
+
+
+def kernel_slope(D, f, cfg):
+    """df/dq inside the support (q = D'^2), from D' and f.  Where f is not
+    differentiable in q (the centre of the kernels with a cusp or a sqrt, and
+    every point outside the support) the slope is 0."""
+    D = np.asarray(D, np.float64)
+    lam = cfg.lambda_
+    k = cfg.kernel
+    inside = f > 0.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        if k == "linear":
+            g = np.where(D > 0.0, -1.0 / (2.0 * lam * D), 0.0)
+        elif k == "gaussian":
+            g = -f / (2.0 * lam * lam)
+        elif k == "laplacian":
+            g = np.where(D > 0.0, -f / (2.0 * lam * D), 0.0)
+        elif k == "cosine":
+            g = np.where(D > 0.0, -np.pi * np.sin(np.pi * D / lam) / (4.0 * lam * D), 0.0)
+        else:   # quadratic
+            g = np.full(D.shape, -1.0 / (lam * lam))
+    return np.where(inside, g, 0.0)
+
+
 def _pair_terms(px, py, mean2d, conic, opac, cfg):
-    """Per (pixel, splat) quantities, all FP64: dx, dy, D, L', o*L', alpha."""
+    """Per (pixel, splat) quantities, all FP64: dx, dy, D, L' (the kernel value
+    f), o*L', alpha."""
     dx = (px[:, None] + 0.5) - mean2d[None, :, 0]
     dy = (py[:, None] + 0.5) - mean2d[None, :, 1]
     A, B, C = conic[None, :, 0], conic[None, :, 1], conic[None, :, 2]
     q = A * dx * dx + 2.0 * B * dx * dy + C * dy * dy
-    D = np.sqrt(np.maximum(q, 0.0))
-    L = np.maximum(0.0, 1.0 - D / cfg.lambda_)
+    D, L = kernel_value(q, cfg)
     raw = opac[None, :] * L
     alpha = np.minimum(cfg.alpha_max, raw)
     return dx, dy, D, L, raw, alpha
@@ -87,6 +137,10 @@ def composite_tile(ids, px, py, mean2d, conic, opac, rgb, cfg, want_pairs=False)
         flag |= (m & (np.abs(raw - amax) < FLAG_REL * amax)).any(axis=1)
         if tmin > 0:
             flag |= (upto & valid & (np.abs(Tincl - tmin) < FLAG_REL * tmin)).any(axis=1)
+        if cfg.kernel == "gaussian":
+            # the 3-sigma cut is a jump of alpha (o * e^-4.5)
+            e2 = extent(cfg) ** 2
+            flag |= (upto & (np.abs(D * D - e2) < FLAG_REL * e2)).any(axis=1)
         any_c = contrib.any(axis=1)
         last_local = np.where(any_c, len(sl) - np.argmax(contrib[:, ::-1], axis=1), 0)
         last = np.where(any_c, k0 + last_local, last)
@@ -147,16 +201,14 @@ def reverse_tile(res, G, mean2d, conic, opac, rgb, cfg, n_splats, GA=None):
     unclamped = raw < cfg.alpha_max
     dL_do = np.where(unclamped, L * dL_dalpha, 0.0)
     dL_dL = np.where(unclamped, opac[ids] * dL_dalpha, 0.0)
-    dL_dD = -dL_dL / cfg.lambda_
+    dL_dq = dL_dL * kernel_slope(D, L, cfg)
     if cfg.ags:
         arg = D if cfg.ags_arg == 0 else D / cfg.lambda_
         omega = np.exp(-arg * arg)
-        dL_dD = dL_dD * omega
+        dL_dq = dL_dq * omega
         if cfg.ags_scope == 1:
             dL_drgb = dL_drgb * omega[:, None]
             dL_do = dL_do * omega
-    with np.errstate(divide="ignore", invalid="ignore"):
-        dL_dq = np.where(D > 0.0, dL_dD / (2.0 * D), 0.0)
     dx, dy = pr["dx"][order], pr["dy"][order]
     A, B, C = conic[ids, 0], conic[ids, 1], conic[ids, 2]
     gc = np.stack([dL_dq * dx * dx, dL_dq * 2.0 * dx * dy, dL_dq * dy * dy], axis=1)
@@ -173,7 +225,6 @@ def composite_bruteforce(width, height, order, mean2d, conic, opac, rgb, cfg):
     splats of the camera in depth order).  For small cases only."""
     C = np.zeros((height, width, 3))
     Tout = np.ones((height, width))
-    lam = cfg.lambda_
     for py in range(height):
         for px in range(width):
             T = 1.0
@@ -182,8 +233,7 @@ def composite_bruteforce(width, height, order, mean2d, conic, opac, rgb, cfg):
                 dx = px + 0.5 - mean2d[i, 0]
                 dy = py + 0.5 - mean2d[i, 1]
                 q = conic[i, 0] * dx * dx + 2.0 * conic[i, 1] * dx * dy + conic[i, 2] * dy * dy
-                D = np.sqrt(max(q, 0.0))
-                a = min(cfg.alpha_max, opac[i] * max(0.0, 1.0 - D / lam))
+                a = min(cfg.alpha_max, opac[i] * float(kernel_value(q, cfg)[1]))
                 if a <= 0.0 or a < cfg.alpha_min:
                     continue
                 Tn = T * (1.0 - a)

@@ -9,6 +9,18 @@ ags_arg   0: omega = exp(-D'^2) with the raw 2D Mahalanobis distance D' (the
 ags_scope 0: omega scales only the gradient that flows through the kernel value
           L' into the geometry (Eq. 14 scales grad L'); 1: omega scales every
           gradient of the (pixel, splat) pair.
+kernel    the attenuation f(D) of the generalised kernel E(x) = f(D(x)) (appendix,
+          "Generalizing the 3DGS Kernel Function"), evaluated at the aligned
+          distance D'/lambda (the DA of Eq. 12 applied to every kernel):
+            linear     max(0, 1 - D)            (the paper's kernel, Eq. 10)
+            gaussian   exp(-D^2 / 2)
+            laplacian  exp(-D)
+            cosine     (1 + cos(pi D)) / 2 for D <= 1, else 0
+            quadratic  max(0, 1 - D^2)
+          A splat's support is D'/lambda < s_f with s_f = 1 for the kernels that
+          reach 0 at D = 1, 3 for the Gaussian (the 3-sigma cut of 3DGS) and
+          ln 255 for the Laplacian (beyond it alpha < 1/255); the binning
+          rectangle bounds the ellipse D' = lambda * s_f (the `extent`).
 The paper leaves the rest unstated (it keeps 3DGS's blending, Sec. 3.2); the
 defaults are the usual 3DGS ones: skip a splat whose alpha is below 1/255,
 clamp alpha at 0.99, stop before a splat that would take transmittance below
@@ -24,6 +36,19 @@ import numpy as np
 
 def _f32(x) -> float:
     return float(np.float32(x))
+
+
+KERNELS = ("linear", "gaussian", "laplacian", "cosine", "quadratic")
+
+# support radius in aligned distance D'/lambda, as the FP32 number both sides use
+SUPPORT = {"linear": _f32(1.0), "gaussian": _f32(3.0), "laplacian": _f32(np.log(255.0)),
+           "cosine": _f32(1.0), "quadratic": _f32(1.0)}
+
+
+def extent(cfg) -> float:
+    """FP32 lambda * s_f: the binning half-extent factor and the support radius
+    in D' (the composite keeps a pair only while D'^2 < extent^2)."""
+    return float(np.float32(np.float32(cfg.lambda_) * np.float32(SUPPORT[cfg.kernel])))
 
 
 @dataclass
@@ -42,8 +67,13 @@ class RasterConfig:
     tile_w: int = 16
     tile_h: int = 16
     bg: tuple = (0.0, 0.0, 0.0)
+    kernel: str = "linear"
 
     def __post_init__(self):
+        if self.kernel not in KERNELS:
+            raise ValueError(f"unknown kernel {self.kernel!r}")
+        if self.ags and self.kernel != "linear":
+            raise ValueError("adaptive gradient scaling (Eq. 13-14) is defined for the linear kernel")
         for name in ("lambda_", "eps2d", "alpha_min", "alpha_max", "t_min",
                      "near", "far", "clip"):
             setattr(self, name, _f32(getattr(self, name)))

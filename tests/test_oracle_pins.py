@@ -12,6 +12,7 @@ import pytest
 import scipy.special as sps
 
 from oracle import RasterConfig, binning, composite, projection, render_forward, render_backward
+from oracle.config import KERNELS
 from oracle import sh as oracle_sh
 from paper_2411_12440_amd import scenes
 
@@ -117,6 +118,57 @@ def test_coverage_integral():
     expect = 0.5 * math.pi / 3.0 * cfg.lambda_ ** 2 * sigma ** 2
     assert sigma * cfg.lambda_ < 120
     assert abs(total / expect - 1) < 2e-4
+
+
+# Sum over pixels of alpha for one isotropic splat against o * lambda^2 sigma^2
+# times the kernel's 2D mass 2 pi int_0^s r f(r) dr up to its support cut s,
+# in closed form: Gaussian 2 pi (1 - e^-4.5), Laplacian 2 pi (1 - e^-L (1 + L))
+# with L = ln 255, raised cosine 2 pi (1/4 - 1/pi^2), quadratic pi / 2, linear
+# pi / 3.  (lambda, scale) keep the support well inside the image; the
+# tolerance covers the pixel sampling of the kernel's cusp or cut.
+_LN255 = float(np.float32(math.log(255.0)))
+FAMILY_MASS = {
+    "linear": (2.5, 0.5, math.pi / 3, 2e-4),
+    "gaussian": (1.0, 0.45, 2 * math.pi * (1 - math.exp(-4.5)), 2e-4),
+    "laplacian": (1.0, 0.25, 2 * math.pi * (1 - math.exp(-_LN255) * (1 + _LN255)), 5e-4),
+    "cosine": (2.5, 0.5, 2 * math.pi * (0.25 - 1 / math.pi ** 2), 1e-4),
+    "quadratic": (6.0, 0.2, math.pi / 2, 1e-4),
+}
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_kernel_family_mass(kernel):
+    lam, s, mass, tol = FAMILY_MASS[kernel]
+    sc, cams, cfg, sigma = _iso_setup(s=s, o=0.5, W=256, H=256, lam=lam, strict=True,
+                                      kernel=kernel)
+    from oracle.config import extent
+    assert extent(cfg) * sigma < 125          # support inside the image
+    fw = render_forward(sc, np.array([0, 1]), cams, cfg)
+    total = (1.0 - fw.final_T).sum()
+    o = float(np.float32(0.5))
+    expect = o * mass * cfg.lambda_ ** 2 * sigma ** 2
+    assert abs(total / expect - 1) < tol, (total, expect)
+
+
+def test_kernel_family_centre_and_cut():
+    """At the splat's centre every kernel gives alpha = o; beyond the support
+    cut none contributes, and inside it the Gaussian still does at its 3-sigma
+    edge (alpha = o e^-4.5 > 1/255 for o = 0.8)."""
+    for kernel in KERNELS:
+        sc, cams, cfg, sigma = _iso_setup(s=0.3, o=0.8, W=65, H=65, lam=1.0, strict=False,
+                                          kernel=kernel)
+        fw = render_forward(sc, np.array([0, 1]), cams, cfg)
+        img = fw.image.reshape(3, 65, 65)
+        # the centre pixel of an odd image sits half a pixel from the splat centre
+        assert abs(img[0, 32, 32] - 0.5 * min(cfg.alpha_max, float(np.float32(0.8)))) < 0.02
+    sc, cams, cfg, sigma = _iso_setup(s=0.05, o=0.8, W=128, H=128, lam=1.0, kernel="gaussian")
+    fw = render_forward(sc, np.array([0, 1]), cams, cfg)
+    a = 1.0 - fw.final_T.reshape(128, 128)
+    ys, xs = np.mgrid[0:128, 0:128]
+    r = np.hypot(xs + 0.5 - 64, ys + 0.5 - 64) / sigma
+    assert np.all(a[r > 3.0 + 1e-6] == 0.0)
+    edge = (r > 2.9) & (r < 3.0 - 1e-6)
+    assert edge.any() and np.all(a[edge] > 1.0 / 255.0)
 
 
 def test_mass_matching_lambda():
@@ -312,10 +364,11 @@ def test_binning_fp32_tracks_fp64():
     assert agree.mean() > 0.999
 
 
-def test_rects_cover_support():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_rects_cover_support(kernel):
     """Every pixel whose FP64 kernel value is above 1e-6 lies in the rect."""
     sc, off, cams = scenes.workload(1)
-    cfg = RasterConfig()
+    cfg = RasterConfig(kernel=kernel)
     fw = render_forward(sc, off, cams, cfg, tiles=[])
     p = fw.proj[0]
     ys, xs = np.mgrid[0:128, 0:128]
@@ -474,11 +527,17 @@ def _rms_close(a, b, rel):
     return np.all(np.abs(a - b) <= rel * (np.abs(b) + rms))
 
 
-@pytest.mark.parametrize("seed,clip", [(0, 1.3), (1, 1.3), (2, 0.2)])
-def test_reverse_pass_against_finite_differences(seed, clip):
-    """clip 0.2 clamps the Jacobian's tangent for several splats."""
+@pytest.mark.parametrize("seed,clip,kernel",
+                         [(0, 1.3, "linear"), (1, 1.3, "linear"), (2, 0.2, "linear"),
+                          (3, 1.3, "gaussian"), (4, 1.3, "laplacian"), (5, 1.3, "cosine"),
+                          (6, 1.3, "quadratic")])
+def test_reverse_pass_against_finite_differences(seed, clip, kernel):
+    """clip 0.2 clamps the Jacobian's tangent for several splats; the other
+    kernels of the family are checked the same way (with their printed DA
+    lambda where the paper gives one, 1 for the Gaussian)."""
     sc, cams, G = _tiny_grad_problem(seed)
-    cfg = RasterConfig.strict(clip=clip)
+    lam = {"linear": 2.5, "gaussian": 1.0, "laplacian": 1.0, "cosine": 2.5, "quadratic": 6.0}
+    cfg = RasterConfig.strict(clip=clip, kernel=kernel, lambda_=lam[kernel])
     if clip < 1:
         fw = render_forward(sc, np.array([0, sc.n]), cams, cfg, tiles=[])
         assert (~fw.proj[0]["u_free"]).sum() >= 3
