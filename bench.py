@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--depth-chunks", type=int, default=7)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-family", action="store_true",
+                    help="skip the linear vs Gaussian kernel comparison")
     return ap.parse_args()
 
 
@@ -304,6 +306,57 @@ def main():
         log(f"bench: per-view {ms_pv:.3f} ms/step, ratio {ms_pv / ms_batched:.3f}")
         del views
 
+    # ---- kernel family: the same step with the Gaussian kernel ------------------
+    family = None
+    if not args.no_family:
+        def time_kernel(kname, lam):
+            kw = dict(cfgkw, kernel=kname, lambda_=lam, ags=False)
+            r = Rasterizer(cams, off, device=dev, capacity=1 << 24, **kw)
+            r.forward(sp, check_capacity=True)
+            torch.cuda.synchronize()
+            r._alloc(max(int(r.n_built() * 1.05) + 4096, r.n_isect() // 12))
+            gr = {k: torch.empty_like(v) for k, v in sp.items()}
+            gph = StepGraph(r, sp, G_all, gr)
+            for _ in range(args.warmup):
+                gph.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                gph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+
+            def eager():
+                r.project(sp)
+                r.bin_sort()
+                r.rasterize_fwd()
+                r.rasterize_bwd(sp, G_all, gr)
+
+            eager()
+            torch.cuda.synchronize()
+            B.ls_profile_read(reset=True)
+            B.ls_profile_enable(True)
+            for _ in range(args.steps):
+                eager()
+            torch.cuda.synchronize()
+            B.ls_profile_enable(False)
+            kt = {n: t / args.steps for n, _, t in B.ls_profile_read(reset=True)}
+            assert not r.overflowed()
+            res = dict(lambda_=lam, ms_per_step=round(ms, 3),
+                       value=round(P / (ms * 1e-3) / 1e6, 3),
+                       raster_fwd_ms=round(kt.get("raster_fwd", 0.0), 3),
+                       raster_bwd_ms=round(kt.get("raster_bwd", 0.0), 3),
+                       entries_built=int(r.n_built()), contributing_pairs=int(r.contributions()))
+            del gph, r, gr
+            return res
+
+        log("bench: kernel family (linear without AGS, Gaussian)")
+        family = {"linear": time_kernel("linear", 2.5), "gaussian": time_kernel("gaussian", 1.0)}
+        family["note"] = ("same scene, cameras and step, both without AGS (defined for the linear "
+                          "kernel only); linear lambda 2.5, Gaussian lambda 1 with the 3-sigma cut")
+        log(f"bench: family {family}")
+
     # ---- roofline of the dominant kernel --------------------------------------
     w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q, Qc=Qc)
     kernels = []
@@ -367,6 +420,7 @@ def main():
                   "value": round(P / (ms_eager * 1e-3) / 1e6, 3),
                   "note": "same step launched eagerly with an event pair around every kernel"},
         "per_view": per_view,
+        "kernel_family": family,
         "roofline": roof,
         "kernels": kernels[:12],
         "cpu_baseline": cpu,

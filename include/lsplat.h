@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 120
+#define LSPLAT_VERSION 130
 
 typedef enum {
   LS_OK = 0,
@@ -57,9 +57,24 @@ typedef enum {
  * lambda     Distribution-alignment factor of Eq. 12 (Sec. 3.3.1): the kernel
  *            is L' = max(0, 1 - D'/lambda) with D' the 2D Mahalanobis distance
  *            of Eq. 11.  The paper uses 2.5; 1.0 is the plain kernel of Eq. 10.
- *            Must be > 0.
+ *            Must be > 0.  With another kernel (below) it scales D' the same
+ *            way: the kernel value is f(D'/lambda).
+ * kernel     The attenuation f of the generalised kernel E(x) = f(D(x)) in the
+ *            appendix ("Generalizing the 3DGS Kernel Function"):
+ *              LS_KERNEL_LINEAR     max(0, 1 - D)      (default, the paper's)
+ *              LS_KERNEL_GAUSSIAN   exp(-D^2 / 2)
+ *              LS_KERNEL_LAPLACIAN  exp(-D)
+ *              LS_KERNEL_COSINE     (1 + cos(pi D)) / 2 for D <= 1, else 0
+ *              LS_KERNEL_QUADRATIC  max(0, 1 - D^2)
+ *            A splat's support is D'/lambda < s_f: s_f = 1, except 3 for the
+ *            Gaussian (the 3-sigma cut of 3DGS) and ln 255 for the Laplacian
+ *            (beyond it alpha < 1/255).  Binning bounds the ellipse
+ *            D' = extent with extent = lambda * s_f rounded to FP32.  The
+ *            appendix's aligned lambdas are 2.5 (cosine, linear), 6
+ *            (quadratic) and 1 (Laplacian); 1 is the plain Gaussian.
  * ags        1: adaptive gradient scaling of Eq. 13-14 (Sec. 3.3.2) in the
- *            backward pass.  The forward pass is unchanged.
+ *            backward pass.  The forward pass is unchanged.  Defined for the
+ *            linear kernel only (LS_ERR_INVALID_ARG with another kernel).
  * ags_arg    0: omega = exp(-D'^2) (raw distance, default); 1: exp(-(D'/lambda)^2).
  * ags_scope  0: omega scales only the gradient through L' into the splat
  *            geometry (default); 1: omega scales every gradient of the pair.
@@ -102,7 +117,16 @@ typedef struct ls_config {
   int32_t tile_w, tile_h;
   int32_t batch;
   int32_t depth_chunks;
+  int32_t kernel;
 } ls_config;
+
+enum {
+  LS_KERNEL_LINEAR = 0,
+  LS_KERNEL_GAUSSIAN = 1,
+  LS_KERNEL_LAPLACIAN = 2,
+  LS_KERNEL_COSINE = 3,
+  LS_KERNEL_QUADRATIC = 4
+};
 
 /*
  * Splats of one or more scenes, concatenated (Sec. 3.1: centre mu, scale S and

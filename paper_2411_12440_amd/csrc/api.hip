@@ -47,6 +47,10 @@ static ls_status check_config(const ls_config* c) {
   if (c->ags_arg != 0 && c->ags_arg != 1) return fail(LS_ERR_INVALID_ARG, "ags_arg must be 0 or 1");
   if (c->ags_scope != 0 && c->ags_scope != 1) return fail(LS_ERR_INVALID_ARG, "ags_scope must be 0 or 1");
   if (c->sh_degree < 0 || c->sh_degree > 3) return fail(LS_ERR_INVALID_ARG, "sh_degree must be 0..3");
+  if (c->kernel < LS_KERNEL_LINEAR || c->kernel > LS_KERNEL_QUADRATIC)
+    return fail(LS_ERR_INVALID_ARG, "kernel must be 0..4 (LS_KERNEL_*)");
+  if (c->ags && c->kernel != LS_KERNEL_LINEAR)
+    return fail(LS_ERR_INVALID_ARG, "ags is defined for the linear kernel only");
   if (!tile_shape_ok(c->tile_w, c->tile_h))
     return fail(LS_ERR_UNSUPPORTED, "tile shape %dx%d not supported (16x16, 16x8, 8x8, 32x8)",
                 c->tile_w, c->tile_h);

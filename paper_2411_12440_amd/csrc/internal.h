@@ -80,6 +80,17 @@ constexpr int kScanThreads = 256;
 constexpr int kKeygenSpan = 2048;   // output entries per key-generation block iteration
 constexpr int kChunkSpan = 1024;    // output entries per chunk-write block iteration
 constexpr int kMaxDepthChunks = 12;
+
+// Support radius of the kernel in aligned distance D'/lambda, and the FP32
+// extent lambda * s_f that bounds the binning ellipse and the composite.
+__host__ __device__ inline float kernel_support(int kernel) {
+  switch (kernel) {
+    case LS_KERNEL_GAUSSIAN: return 3.0f;
+    case LS_KERNEL_LAPLACIAN: return 5.541263545158426f;   // ln 255
+    default: return 1.0f;
+  }
+}
+inline float kernel_extent(const ls_config* cfg) { return cfg->lambda * kernel_support(cfg->kernel); }
 constexpr int kMaxScanBlocks = 1024;
 
 // ---------------------------------------------------------------------------

@@ -607,7 +607,7 @@ hipError_t launch_project(const Plan& p, const ls_config* cfg, const ls_splats* 
   dim3 grid((unsigned)((p.N + kProjThreads - 1) / kProjThreads));
 #define LS_PROJ(D)                                                                               \
   hipLaunchKernelGGL(project_kernel<D>, grid, dim3(kProjThreads), 0, s, cams, p.C, p.N, sp->means, \
-                     sp->scales, sp->quats, sp->opacity, sp->sh, cfg->lambda, cfg->eps2d,         \
+                     sp->scales, sp->quats, sp->opacity, sp->sh, kernel_extent(cfg), cfg->eps2d,         \
                      cfg->clip, cfg->near_z, cfg->far_z, cfg->tile_w, cfg->tile_h,              \
                      (ProjRec*)(ws + p.lay.proj), (ushort4*)(ws + p.lay.rect),                  \
                      (uint32_t*)(ws + p.lay.ntiles), (uint32_t*)(ws + p.lay.depth_key))

@@ -1,4 +1,7 @@
-// Per-tile compositing with the linear kernel (forward) and its reverse pass.
+// Per-tile compositing with the linear kernel (forward) and its reverse pass;
+// the other kernels of the appendix's family (Gaussian, Laplacian, raised
+// cosine, quadratic, each with alignment lambda) are template instances of
+// the same kernels.
 //
 // Forward (Eq. 6 with Eq. 10-12): alpha = min(alpha_max, o * max(0, 1 - D'/lambda)),
 // D'^2 = A dx^2 + 2B dx dy + C dy^2.  Blending rules kept from 3DGS (Sec. 3.2):
@@ -9,18 +12,19 @@
 // per-pair 2D gradients; adaptive gradient scaling (Eq. 13-14) multiplies the
 // gradient through L' by omega(D') = exp(-D'^2).
 //
-// One workgroup per tile, one lane per pixel (wave64: a 16x16 tile is four
-// waves of 16x4 pixels).  The tile's list is consumed in batches staged in
-// LDS (gathered 64-byte records, converted to tile-relative FP64 centres).
+// One workgroup per tile, one or two pixels per lane (wave64: a 16x16 tile
+// is two waves of 16x8 pixels).  The tile's list is consumed in batches
+// staged in LDS (gathered 64-byte records, turned into the coefficients of
+// the quadratic form in tile-local coordinates).
 // Blocks are remapped so that each XCD (blocks are dealt round-robin over
 // the 8 XCDs) works on one contiguous band of tiles and keeps the records of
 // neighbouring tiles in its own L2.
 //
-// Numerics: the quadratic form is evaluated in FP64 (full rate on CDNA, and
-// free of the FP32 cancellation of needle-shaped splats); everything after
-// D'^2 is FP32.  1 - alpha is formed as (1 - o) + o D'/lambda, a sum of two
-// non-negative terms, so transmittance keeps full relative precision when
-// alpha is close to 1.
+// Numerics: the quadratic form, D', alpha, the transmittance and colour
+// state and every backward term are FP64 (full rate on CDNA, and free of the
+// FP32 cancellation of needle-shaped splats).  1 - alpha is formed as
+// (1 - o) + o D'/lambda, a sum of two non-negative terms, so transmittance
+// keeps full relative precision when alpha is close to 1.
 #include <algorithm>
 
 #include "internal.h"
@@ -38,46 +42,9 @@ struct RasterParams {
   int ags, ags_arg, ags_scope;
   int exp_tab;        // the AGS weight of every contributing pair can use exp_neg_tab
   double ags_scale;   // AGS exponent per unit D'^2: 1 / lambda^2 or 1
+  double qmax;        // extent^2: a pair is kept while D'^2 < qmax (the support)
+  double ghalf;       // 1 / (2 lambda^2), the Gaussian's exponent per unit D'^2
 };
-
-// alpha and 1 - alpha of one (pixel, splat) pair, in FP64.  Shared by the
-// forward and backward kernels and evaluated without contraction, so both
-// kernels take every skip/stop decision identically.
-struct PairEval {
-  double D, alpha, oma;
-  double invD;   // 1 / D (meaningful only for D > 0; the forward pass ignores it)
-  bool clamped;
-};
-
-// sqrt(q) for q >= 0 (a negative q, possible only by rounding of the
-// expanded quadratic form at a splat's centre, counts as 0): the FP32
-// reciprocal square root as a start and one FP64 Newton step, which brings
-// the relative error from about 2^-22 to below 1e-13.  Below 1e-30 the result
-// is 0 (an absolute error under 1e-15).
-// The same start gives 1/sqrt(q) with one Newton step for the reciprocal
-// square root.
-__device__ __forceinline__ double sqrt_nonneg(double q, double* inv) {
-  const double y = (double)__builtin_amdgcn_rsqf((float)q);
-  *inv = y * fma(-0.5 * q, y * y, 1.5);
-  if (!(q > 1e-30)) return 0.0;
-  const double d0 = q * y;
-  return fma(0.5 * y, fma(-d0, d0, q), d0);
-}
-
-__device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterParams& rp) {
-#pragma clang fp contract(off)
-  PairEval e;
-  e.D = sqrt_nonneg(q, &e.invD);
-  const double t = o * (e.D * rp.inv_lam);
-  e.alpha = o - t;
-  e.oma = (1.0 - o) + t;
-  e.clamped = e.alpha > rp.amax;
-  if (e.clamped) {
-    e.alpha = rp.amax;
-    e.oma = rp.oma_max;
-  }
-  return e;
-}
 
 // e^-x for x >= 0 in FP64: x = k ln2/2 + r with |r| <= ln2 / 4 (ln2/2 split
 // in a high part whose products with k are exact and a low part), e^-r from
@@ -125,6 +92,88 @@ __device__ __forceinline__ double exp_neg_tab(double x, const double* tab) {
   return tab[j] * p;
 }
 
+
+// alpha and 1 - alpha of one (pixel, splat) pair, in FP64.  Shared by the
+// forward and backward kernels and evaluated without contraction, so both
+// kernels take every skip/stop decision identically.
+struct PairEval {
+  double D, alpha, oma;
+  double invD;   // 1 / D (meaningful only for D > 0; the forward pass ignores it)
+  double f;      // kernel value f(D/lambda) (alpha = o f below the clamp)
+  double sx;     // raised cosine: sin(pi D/lambda), for its slope
+  bool clamped;
+};
+
+// sqrt(q) for q >= 0 (a negative q, possible only by rounding of the
+// expanded quadratic form at a splat's centre, counts as 0): the FP32
+// reciprocal square root as a start and one FP64 Newton step, which brings
+// the relative error from about 2^-22 to below 1e-13.  Below 1e-30 the result
+// is 0 (an absolute error under 1e-15).
+// The same start gives 1/sqrt(q) with one Newton step for the reciprocal
+// square root.
+__device__ __forceinline__ double sqrt_nonneg(double q, double* inv) {
+  const double y = (double)__builtin_amdgcn_rsqf((float)q);
+  *inv = y * fma(-0.5 * q, y * y, 1.5);
+  if (!(q > 1e-30)) return 0.0;
+  const double d0 = q * y;
+  return fma(0.5 * y, fma(-d0, d0, q), d0);
+}
+
+// Kernels of the family (LS_KERNEL_*), a template parameter of the raster
+// kernels.  The ones that fall to 0 (linear, quadratic) form 1 - alpha as
+// (1 - o) + o (1 - f), a sum of non-negative terms; the others as 1 - o f.
+// The exponential kernels read e^-x from the LDS table `tab`.
+template <int KF>
+constexpr bool kernel_uses_exp() {
+  return KF == LS_KERNEL_GAUSSIAN || KF == LS_KERNEL_LAPLACIAN;
+}
+
+template <int KF>
+__device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterParams& rp,
+                                              const double* tab) {
+#pragma clang fp contract(off)
+  PairEval e;
+  e.sx = 0.0;
+  if constexpr (KF == LS_KERNEL_LINEAR) {
+    e.D = sqrt_nonneg(q, &e.invD);
+    const double t = o * (e.D * rp.inv_lam);
+    e.alpha = o - t;
+    e.oma = (1.0 - o) + t;
+    e.f = 1.0 - e.D * rp.inv_lam;
+  } else if constexpr (KF == LS_KERNEL_QUADRATIC) {
+    e.D = 0.0;
+    e.invD = 0.0;
+    const double u = fmax(q, 0.0) * rp.inv_lam2;
+    const double t = o * u;
+    e.alpha = o - t;
+    e.oma = (1.0 - o) + t;
+    e.f = 1.0 - u;
+  } else if constexpr (KF == LS_KERNEL_GAUSSIAN) {
+    e.D = 0.0;
+    e.invD = 0.0;
+    e.f = exp_neg_tab(fmax(q, 0.0) * rp.ghalf, tab);
+    e.alpha = o * e.f;
+    e.oma = 1.0 - e.alpha;
+  } else if constexpr (KF == LS_KERNEL_LAPLACIAN) {
+    e.D = sqrt_nonneg(q, &e.invD);
+    e.f = exp_neg_tab(e.D * rp.inv_lam, tab);
+    e.alpha = o * e.f;
+    e.oma = 1.0 - e.alpha;
+  } else {   // raised cosine
+    e.D = sqrt_nonneg(q, &e.invD);
+    double cs;
+    sincospi(fmin(e.D * rp.inv_lam, 1.0), &e.sx, &cs);
+    e.f = 0.5 * (1.0 + cs);
+    e.alpha = o * e.f;
+    e.oma = 1.0 - e.alpha;
+  }
+  e.clamped = e.alpha > rp.amax;
+  if (e.clamped) {
+    e.alpha = rp.amax;
+    e.oma = rp.oma_max;
+  }
+  return e;
+}
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   const int64_t x = b & 7, k = b >> 3;
@@ -259,7 +308,7 @@ constexpr int raster_threads() { return TW * TH / raster_ppl<TW, TH>(); }
 // The forward pass is bound by the latency of its global reads (tile
 // state, staged records): seven waves per SIMD instead of the five its
 // registers would allow (a few values live across the loop go to scratch).
-template <int TW, int TH>
+template <int TW, int TH, int KF>
 __global__ __launch_bounds__((raster_threads<TW, TH>())) __attribute__((amdgpu_waves_per_eu(7)))
 void raster_fwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all, int64_t T_all,
@@ -273,9 +322,12 @@ void raster_fwd_kernel(
   constexpr int NWB = NTB / 64;
   __shared__ Stage<NTB, NWB> st;
   __shared__ uint32_t s_cnt[NWB];
+  __shared__ double s_exptab[kernel_uses_exp<KF>() ? kExpTabN : 1];
   const int tid = threadIdx.x;
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   if (c > 0 && alive[tile] == 0u) return;
+  if constexpr (kernel_uses_exp<KF>())   // ready at the first batch's barriers
+    for (int i = tid; i < kExpTabN; i += NTB) s_exptab[i] = exp_neg((double)i / kExpTabStep);
   const int64_t* ranges = ranges_all + (int64_t)c * (T_all + 1);
   const int32_t len = (int32_t)(ranges[tile + 1] - ranges[tile]);
   if (c > 0 && len == 0) return;
@@ -333,7 +385,7 @@ void raster_fwd_kernel(
     if (__syncthreads_count(!all_done()) == 0) break;
     const int nb = (len - p0) < bsz ? (len - p0) : bsz;
     const int cnt = stage_batch<TW, TH, NTB, NWB>(st, vals, proj, M, tid < nb, start + p0 + tid,
-                                                  prefix + p0 + tid, x0c, y0c, rp.lam2);
+                                                  prefix + p0 + tid, x0c, y0c, rp.qmax);
     if (!all_done()) {
       for (int k = 0; k < cnt; ++k) {
         const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
@@ -342,8 +394,8 @@ void raster_fwd_kernel(
         for (int j = 0; j < PPL; ++j) {
           if (done[j]) continue;
           const double q = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
-          if (!(q < rp.lam2)) continue;
-          const PairEval e = pair_eval(q, (double)st.o[k], rp);
+          if (!(q < rp.qmax)) continue;
+          const PairEval e = pair_eval<KF>(q, (double)st.o[k], rp, s_exptab);
           if (!(e.alpha > 0.0) || e.alpha < rp.amin) continue;
           const double Tn = T[j] * e.oma;
           if (Tn < rp.tmin) {
@@ -395,7 +447,7 @@ void raster_fwd_kernel(
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int KF>
 __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all,
     int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
@@ -416,7 +468,7 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   __shared__ double s_exptab[kExpTabN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (rp.ags && rp.exp_tab)
+  if (kernel_uses_exp<KF>() || (rp.ags && rp.exp_tab))
     for (int i = tid; i < kExpTabN; i += NTB) s_exptab[i] = exp_neg((double)i / kExpTabStep);
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int c = cam_of_tile(cams, C, tile);
@@ -498,7 +550,7 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
       vidx = s_segbase[cc] + (q - s_segpre[cc]);
     }
     const int cnt =
-        stage_batch<TW, TH, NS, NWB>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.lam2);
+        stage_batch<TW, TH, NS, NWB>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.qmax);
     for (int i = tid; i < kGrad2d * NS; i += NTB) (&s_acc[0][0])[i] = 0.0;
     __syncthreads();
     // the staged positions increase with k: the entries this wave needs are
@@ -523,8 +575,8 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         qq[j] = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
-        e[j] = pair_eval(qq[j], o, rp);
-        contrib[j] = pos < mylast[j] && qq[j] < rp.lam2 && e[j].alpha > 0.0 &&
+        e[j] = pair_eval<KF>(qq[j], o, rp, s_exptab);
+        contrib[j] = pos < mylast[j] && qq[j] < rp.qmax && e[j].alpha > 0.0 &&
                      e[j].alpha >= rp.amin;
         any = any || contrib[j];
       }
@@ -560,9 +612,21 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
         // would amplify the sum's rounding for elongated splats.
         // The masks act on the per-pair factors (gq, the opacity factor and
         // w), so that a masked pair adds exact zeros to the sums.
-        const bool geo = contrib[j] && !e[j].clamped && e[j].D > 0.0;
-        // dL/dq = dL/dalpha (-o / lambda) omega / (2 D)
-        const double gq = geo ? nol * dLda * om * e[j].invD : 0.0;
+        // dL/dq = dL/dalpha o f'(q): linear -omega / (2 lambda D); Gaussian
+        // -f / (2 lambda^2); quadratic -1 / lambda^2; Laplacian
+        // -f / (2 lambda D); raised cosine -pi sin(pi D/lambda) / (4 lambda D)
+        // (the kernels with D in f' take no gradient at D = 0)
+        constexpr bool needs_d = KF == LS_KERNEL_LINEAR || KF == LS_KERNEL_LAPLACIAN ||
+                                 KF == LS_KERNEL_COSINE;
+        const bool geo = contrib[j] && !e[j].clamped && (!needs_d || e[j].D > 0.0);
+        double gq;
+        if constexpr (KF == LS_KERNEL_LINEAR) gq = nol * dLda * om * e[j].invD;
+        else if constexpr (KF == LS_KERNEL_GAUSSIAN) gq = -(dLda * e[j].alpha) * rp.ghalf;
+        else if constexpr (KF == LS_KERNEL_QUADRATIC) gq = -(o * dLda) * rp.inv_lam2;
+        else if constexpr (KF == LS_KERNEL_LAPLACIAN)
+          gq = -0.5 * (dLda * e[j].alpha) * rp.inv_lam * e[j].invD;
+        else gq = -0.7853981633974483 * (o * dLda) * rp.inv_lam * e[j].sx * e[j].invD;   // pi/4
+        gq = geo ? gq : 0.0;
         // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
         const double ux = fma(A, lx, fma(B, ly[j], 0.5 * qd));
         const double uy = fma(B, lx, fma(Cc, ly[j], 0.5 * qe));
@@ -574,7 +638,7 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
         gv[3] = fma(-2.0 * gux, uy, gv[3]);
         gv[4] = fma(-guy, uy, gv[4]);
         const double go = (contrib[j] && !e[j].clamped) ? dLda * sc : 0.0;
-        gv[5] = fma(1.0 - e[j].D * rp.inv_lam, go, gv[5]);
+        gv[5] = fma(e[j].f, go, gv[5]);
         const double wsc = contrib[j] ? w * sc : 0.0;
         gv[6] += wsc * G0[j];
         gv[7] += wsc * G1[j];
@@ -611,8 +675,11 @@ __global__ void zero_kernel(float* __restrict__ p, int64_t n) {
 RasterParams make_params(const ls_config* cfg) {
   RasterParams rp;
   rp.lam2 = (double)cfg->lambda * (double)cfg->lambda;
+  const double ext = (double)kernel_extent(cfg);
+  rp.qmax = ext * ext;
   rp.inv_lam = 1.0 / (double)cfg->lambda;
   rp.inv_lam2 = rp.inv_lam * rp.inv_lam;
+  rp.ghalf = 0.5 * rp.inv_lam2;
   rp.amin = cfg->alpha_min;
   rp.amax = cfg->alpha_max;
   rp.oma_max = 1.0 - (double)cfg->alpha_max;
@@ -662,15 +729,23 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
   for (int c = 0; c < p.K; ++c) {
     if (p.K > 1 && (e = launch_chunk_bin(p, c, ws, s))) return e;
     ProfScope ps("raster_fwd", s);
-#define LS_FWD(TW_, TH_)                                                                           \
-  hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_>), grid, dim3(raster_threads<TW_, TH_>()), 0, s,   \
-                     cams, p.C, ranges, \
-                     p.T, c, p.K, chunk_base, vals, proj, p.M, batch, rp, state, done, alive, image, \
-                     final_T, last, tile_contrib)
-    if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_FWD(16, 16);
-    else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_FWD(16, 8);
-    else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_FWD(8, 8);
-    else LS_FWD(32, 8);
+#define LS_FWD(TW_, TH_, KF_)                                                                      \
+  hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_, KF_>), grid, dim3(raster_threads<TW_, TH_>()), 0, \
+                     s, cams, p.C, ranges, p.T, c, p.K, chunk_base, vals, proj, p.M, batch, rp,      \
+                     state, done, alive, image, final_T, last, tile_contrib)
+#define LS_FWD_K(TW_, TH_)                                                                         \
+  switch (cfg->kernel) {                                                                           \
+    case LS_KERNEL_GAUSSIAN: LS_FWD(TW_, TH_, LS_KERNEL_GAUSSIAN); break;                          \
+    case LS_KERNEL_LAPLACIAN: LS_FWD(TW_, TH_, LS_KERNEL_LAPLACIAN); break;                        \
+    case LS_KERNEL_COSINE: LS_FWD(TW_, TH_, LS_KERNEL_COSINE); break;                              \
+    case LS_KERNEL_QUADRATIC: LS_FWD(TW_, TH_, LS_KERNEL_QUADRATIC); break;                        \
+    default: LS_FWD(TW_, TH_, LS_KERNEL_LINEAR); break;                                           \
+  }
+    if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_FWD_K(16, 16)
+    else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_FWD_K(16, 8)
+    else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_FWD_K(8, 8)
+    else LS_FWD_K(32, 8)
+#undef LS_FWD_K
 #undef LS_FWD
     if ((e = hipGetLastError())) return e;
   }
@@ -698,15 +773,23 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     const int batch = cfg->batch ? cfg->batch : npix;
     dim3 grid((unsigned)p.T);
     ProfScope ps("raster_bwd", s);
-#define LS_BWD(TW_, TH_)                                                                         \
-  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_>), grid, dim3(raster_threads<TW_, TH_>()), 0, s, cams, \
-                     p.C, ranges, \
-                     p.T, p.K, chunk_base, vals, proj, p.M, batch, rp, final_T, last, dL_dimage, \
-                     dL_dalpha, grad2d)
-    if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_BWD(16, 16);
-    else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_BWD(16, 8);
-    else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_BWD(8, 8);
-    else LS_BWD(32, 8);
+#define LS_BWD(TW_, TH_, KF_)                                                                      \
+  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_>), grid, dim3(raster_threads<TW_, TH_>()), 0, \
+                     s, cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,         \
+                     final_T, last, dL_dimage, dL_dalpha, grad2d)
+#define LS_BWD_K(TW_, TH_)                                                                         \
+  switch (cfg->kernel) {                                                                           \
+    case LS_KERNEL_GAUSSIAN: LS_BWD(TW_, TH_, LS_KERNEL_GAUSSIAN); break;                          \
+    case LS_KERNEL_LAPLACIAN: LS_BWD(TW_, TH_, LS_KERNEL_LAPLACIAN); break;                        \
+    case LS_KERNEL_COSINE: LS_BWD(TW_, TH_, LS_KERNEL_COSINE); break;                              \
+    case LS_KERNEL_QUADRATIC: LS_BWD(TW_, TH_, LS_KERNEL_QUADRATIC); break;                        \
+    default: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR); break;                                           \
+  }
+    if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_BWD_K(16, 16)
+    else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_BWD_K(16, 8)
+    else if (cfg->tile_w == 8 && cfg->tile_h == 8) LS_BWD_K(8, 8)
+    else LS_BWD_K(32, 8)
+#undef LS_BWD_K
 #undef LS_BWD
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

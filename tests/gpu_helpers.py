@@ -26,7 +26,8 @@ def cfg_pair(**kw):
     okw = dict(lambda_=kw.get("lambda_", 2.5), ags=kw.get("ags", False),
                ags_arg=kw.get("ags_arg", 0), ags_scope=kw.get("ags_scope", 0),
                tile_w=kw.get("tile_w", 16), tile_h=kw.get("tile_h", 16),
-               bg=kw.get("bg", (0.0, 0.0, 0.0)), clip=kw.get("clip", 1.3))
+               bg=kw.get("bg", (0.0, 0.0, 0.0)), clip=kw.get("clip", 1.3),
+               kernel=kw.get("kernel", "linear"))
     if strict:
         okw.update(alpha_min=0.0, t_min=0.0)
     ocfg = RasterConfig(**okw)
@@ -34,7 +35,8 @@ def cfg_pair(**kw):
                alpha_max=ocfg.alpha_max, t_min=ocfg.t_min, near=ocfg.near, far=ocfg.far,
                clip=ocfg.clip, bg=ocfg.bg, ags=ocfg.ags, ags_arg=ocfg.ags_arg,
                ags_scope=ocfg.ags_scope, tile_w=ocfg.tile_w, tile_h=ocfg.tile_h,
-               batch=kw.get("batch", 0), depth_chunks=kw.get("depth_chunks", 1))
+               batch=kw.get("batch", 0), depth_chunks=kw.get("depth_chunks", 1),
+               kernel=ocfg.kernel)
     return ocfg, gkw
 
 

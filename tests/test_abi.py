@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(B.EXPORTS) == set(declared_functions())
-    assert B.ls_version() == 120
+    assert B.ls_version() == 130
 
 
 def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):
@@ -64,7 +64,7 @@ def test_workspace_size_and_layout():
 @pytest.mark.parametrize("field,value", [("lambda_", 0.0), ("eps2d", 0.0), ("alpha_max", 1.0),
                                          ("t_min", -1.0), ("sh_degree", 4), ("ags", 2),
                                          ("batch", 100), ("near_z", -1.0),
-                                         ("depth_chunks", 13)])
+                                         ("depth_chunks", 13), ("kernel", 5), ("kernel", -1)])
 def test_invalid_config_rejected(field, value):
     from paper_2411_12440_amd import binding as B
     cfg = B.make_config()
@@ -73,6 +73,15 @@ def test_invalid_config_rejected(field, value):
         B.ls_workspace_size(cfg, _cams(), 0)
     assert ei.value.status in (-1, -4)
     assert len(B.LIB.ls_last_error()) > 0
+
+
+def test_ags_needs_the_linear_kernel():
+    from paper_2411_12440_amd import binding as B
+    cfg = B.make_config(ags=True, kernel="gaussian")
+    with pytest.raises(B.LsError) as ei:
+        B.ls_workspace_size(cfg, _cams(), 0)
+    assert ei.value.status == -1
+    B.ls_workspace_size(B.make_config(kernel="gaussian"), _cams(), 0)
 
 
 def test_invalid_cameras_rejected():

@@ -92,6 +92,31 @@ def test_forward_backward_small(ags, ags_arg, ags_scope, strict, chunks, lam):
     compare_grads(grads, go, scene)
 
 
+# the appendix's kernel family, each with its printed alignment lambda (1 for
+# the Gaussian), under complete lists and depth chunks, and two tile shapes
+@pytest.mark.parametrize("kernel,lam,chunks,tw,th",
+                         [("gaussian", 1.0, 1, 16, 16), ("gaussian", 1.0, 4, 16, 8),
+                          ("laplacian", 1.0, 1, 16, 16), ("laplacian", 1.0, 3, 8, 8),
+                          ("cosine", 2.5, 1, 16, 16), ("cosine", 2.5, 3, 32, 8),
+                          ("quadratic", 6.0, 1, 16, 16), ("quadratic", 6.0, 4, 16, 8)])
+def test_kernel_family_forward_backward(kernel, lam, chunks, tw, th):
+    say(f"case: {kernel} lambda={lam} fwd+bwd 3000 splats SH3 200x120 chunks={chunks} "
+        f"tile {tw}x{th}")
+    scene = scenes.make_scene(3000, 78, -3.0, 0.5, 3)
+    cams = scenes.front_camera(200, 120)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair(kernel=kernel, lambda_=lam, bg=(0.1, 0.2, 0.3), depth_chunks=chunks,
+                         tile_w=tw, tile_h=th)
+    G = scenes.upstream_grad(cams, 7012)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    G = G * ~pixel_flags_to_image(fw.flag, cams)
+    g, grads = _run_fwd_bwd(scene, off, cams, gkw, G)
+    compare_binning(g, fw)
+    compare_forward(g, fw, cams)
+    go = render_backward(fw, scene, cams, G)
+    compare_grads(grads, go, scene)
+
+
 @pytest.mark.parametrize("chunks", [1, 3])
 def test_multi_camera_multi_scene(chunks):
     say(f"case: 3 scenes, 6 cameras of uneven size, fwd+bwd, depth chunks {chunks}")
