@@ -25,6 +25,8 @@ Every function here is plain and slow on purpose.  Modules:
   binning     FP32 binning sequence, intersection list, sort, tile ranges
   composite   tiled composite (forward + reverse) and brute-force composite
   render      whole-path driver over cameras and scenes
+  loss        the training loss (L1, L2, SSIM; implementation section) and its
+              gradient with respect to the rendered image
 """
 from .config import RasterConfig  # noqa: F401
 from .render import render_forward, render_backward  # noqa: F401
