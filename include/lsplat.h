@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 130
+#define LSPLAT_VERSION 140
 
 typedef enum {
   LS_OK = 0,
@@ -312,6 +312,37 @@ ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* splats,
                            int64_t isect_capacity, const float* final_T, const int32_t* last,
                            const float* dL_dimage, const float* dL_dalpha,
                            const ls_grads* grads, void* stream);
+
+/*
+ * Training loss of Sec. 4.1 ("Loss Functions") and its gradient with respect
+ * to the rendered image.  For each camera c, over its 3 x H_c x W_c image x
+ * and target y (N_c = 3 H_c W_c values):
+ *   loss[c] = 0.6 mean|x - y| + 0.2 mean (x - y)^2 + 0.2 (1 - SSIM),
+ * where SSIM is the mean over channels and pixels of the SSIM map of Wang et
+ * al. (2004) with local moments from an 11 x 11 Gaussian window of sigma 1.5
+ * (weights summing to 1), zero padding at the border (no renormalisation
+ * there), C1 = 0.01^2 and C2 = 0.03^2.  The paper fixes the weights and the
+ * three terms; the window, padding and constants are the ones its 3DGS
+ * baseline trains with.  The derivative of |x - y| at x = y is taken as 0.
+ * cams       only n_cams, h_width and h_height are read (same checks as the
+ *            other entry points: 1..65535 cameras, sizes 1..16384).
+ * image      [sum_c 3 H_c W_c] device, the layout ls_rasterize_fwd writes
+ *            (per camera, three planes of H_c x W_c, row-major).
+ * target     [sum_c 3 H_c W_c] device, same layout.
+ * dL_dimage  [sum_c 3 H_c W_c] device out: d loss[c] / d image for each
+ *            camera's own pixels (written, not accumulated).  It may be
+ *            passed straight to ls_rasterize_bwd: the gradient of the sum of
+ *            the per-camera losses.
+ * loss       [n_cams] device out, FP64.
+ * ws         device workspace of at least ls_loss_workspace_size() bytes,
+ *            256-byte aligned, owned by the caller; independent of the
+ *            rasterizer's workspace.  Nothing is allocated.
+ * Enqueued on `stream` (NULL = the null stream); returns LS_ERR_INVALID_ARG
+ * or LS_ERR_WORKSPACE before launching anything when an argument is wrong.
+ */
+ls_status ls_loss_workspace_size(const ls_cameras* cams, size_t* bytes);
+ls_status ls_loss(const ls_cameras* cams, const float* image, const float* target,
+                  float* dL_dimage, double* loss, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Kernel timing (tracing).  While enabled, every kernel the library enqueues

@@ -89,6 +89,9 @@ def _load() -> C.CDLL:
         "ls_rasterize_bwd": ([P(Config), P(Splats), P(Cams), C.c_void_p, C.c_size_t, C.c_int64,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(Grads), C.c_void_p],
                              C.c_int),
+        "ls_loss_workspace_size": ([P(Cams), P(C.c_size_t)], C.c_int),
+        "ls_loss": ([P(Cams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.c_size_t, C.c_void_p], C.c_int),
         "ls_profile_enable": ([C.c_int], C.c_int),
         "ls_profile_read": ([P(KernelTime), C.c_int, P(C.c_int), C.c_int], C.c_int),
     }
@@ -102,7 +105,7 @@ def _load() -> C.CDLL:
 LIB = _load()
 EXPORTS = ("ls_version", "ls_last_error", "ls_workspace_size", "ls_workspace_layout",
            "ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd",
-           "ls_profile_enable", "ls_profile_read")
+           "ls_loss_workspace_size", "ls_loss", "ls_profile_enable", "ls_profile_read")
 
 
 def _check(st: int):
@@ -196,6 +199,17 @@ def ls_rasterize_bwd(cfg, splats: Splats, cams: CamerasHost, ws, capacity, final
                                 ws.numel(), capacity, _ptr(final_T), _ptr(last),
                                 _ptr(dL_dimage), _ptr(dL_dalpha), C.byref(grads),
                                 _stream(stream)))
+
+
+def ls_loss_workspace_size(cams: CamerasHost) -> int:
+    out = C.c_size_t(0)
+    _check(LIB.ls_loss_workspace_size(C.byref(cams.c), C.byref(out)))
+    return out.value
+
+
+def ls_loss(cams: CamerasHost, image, target, dL_dimage, loss, ws, stream=None):
+    _check(LIB.ls_loss(C.byref(cams.c), _ptr(image), _ptr(target), _ptr(dL_dimage), _ptr(loss),
+                       _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def ls_profile_enable(on: bool = True):

@@ -1,6 +1,6 @@
 // C-ABI entry points of liblsplat: argument validation, workspace planning and
-// the enqueue of each stage.  Kernels live in project.hip, binsort.hip and
-// raster.hip.
+// the enqueue of each stage.  Kernels live in project.hip, binsort.hip,
+// raster.hip and (the training loss) loss.hip.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -199,6 +199,21 @@ static ls_status check_splats(const ls_config* cfg, const Plan& p, const ls_spla
   return LS_OK;
 }
 
+static ls_status check_loss_cams(const ls_cameras* cams, int64_t* P) {
+  if (!cams) return fail(LS_ERR_INVALID_ARG, "cams is NULL");
+  if (cams->n_cams < 1 || cams->n_cams > 65535) return fail(LS_ERR_INVALID_ARG, "n_cams must be 1..65535");
+  if (!cams->h_width || !cams->h_height) return fail(LS_ERR_INVALID_ARG, "camera host arrays must not be NULL");
+  int64_t n = 0;
+  for (int c = 0; c < cams->n_cams; ++c) {
+    const int w = cams->h_width[c], h = cams->h_height[c];
+    if (w < 1 || h < 1 || w > 16384 || h > 16384)
+      return fail(LS_ERR_INVALID_ARG, "camera %d: image size %dx%d outside 1..16384", c, w, h);
+    n += (int64_t)w * h;
+  }
+  *P = n;
+  return LS_OK;
+}
+
 }  // namespace lsplat
 
 using namespace lsplat;
@@ -284,6 +299,32 @@ ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* sp, const ls_c
   hipError_t e = launch_raster_bwd(p, cfg, sp, (char*)ws, final_T, last, dL_dimage, dL_dalpha,
                                    g, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "rasterize_bwd");
+  return LS_OK;
+}
+
+ls_status ls_loss_workspace_size(const ls_cameras* cams, size_t* bytes) {
+  if (!bytes) return fail(LS_ERR_INVALID_ARG, "bytes is NULL");
+  int64_t P = 0;
+  ls_status st = check_loss_cams(cams, &P);
+  if (st != LS_OK) return st;
+  *bytes = loss_workspace_bytes(P, cams->n_cams);
+  return LS_OK;
+}
+
+ls_status ls_loss(const ls_cameras* cams, const float* image, const float* target,
+                  float* dL_dimage, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  int64_t P = 0;
+  ls_status st = check_loss_cams(cams, &P);
+  if (st != LS_OK) return st;
+  if (!image || !target || !dL_dimage || !loss)
+    return fail(LS_ERR_INVALID_ARG, "image/target/dL_dimage/loss is NULL");
+  if (!ws) return fail(LS_ERR_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256) return fail(LS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  const size_t need = loss_workspace_bytes(P, cams->n_cams);
+  if (ws_bytes < need) return fail(LS_ERR_WORKSPACE, "workspace has %zu bytes, loss needs %zu", ws_bytes, need);
+  hipError_t e = launch_loss(cams->h_width, cams->h_height, cams->n_cams, image, target, dL_dimage,
+                             loss, (char*)ws, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "loss");
   return LS_OK;
 }
 

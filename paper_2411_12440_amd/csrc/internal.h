@@ -253,6 +253,10 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
                              float* final_T, int32_t* last, hipStream_t s);
 hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                               const ls_grads* g, hipStream_t s);
+size_t loss_workspace_bytes(int64_t P, int C);
+hipError_t launch_loss(const int32_t* W, const int32_t* H, int C, const float* image,
+                       const float* target, float* dL_dimage, double* loss, char* ws,
+                       hipStream_t s);
 hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                              const float* final_T, const int32_t* last, const float* dL_dimage,
                              const float* dL_dalpha, const ls_grads* g, hipStream_t s);

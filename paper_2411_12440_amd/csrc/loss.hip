@@ -1,0 +1,273 @@
+// Training loss of the implementation section (Sec. 4.1, "Loss Functions"):
+// per camera L = 0.6 L1 + 0.2 L2 + 0.2 (1 - SSIM) over its 3 x H x W image,
+// and dL/dimage.  SSIM (Wang et al. 2004) with an 11 x 11 Gaussian window of
+// sigma 1.5 (normalised), zero padding, C1 = 0.01^2, C2 = 0.03^2.
+//
+// Two passes, each over 32 x 16 pixel tiles of one channel (up to 16 cameras
+// per launch, one block per tile and channel) with a
+// 5-pixel halo staged in LDS and the window applied separably (a row pass
+// into LDS, then a column pass), all in FP64 (full rate on CDNA; the local
+// variances sxx - mx^2 cancel badly in FP32):
+//   1. local moments mx, my, sxx, syy, sxy; the SSIM map S and its partial
+//      derivatives dS/dmx, dS/dsxx, dS/dsxy (written per pixel, FP64), and
+//      the block's sums of S, |x - y|, (x - y)^2 (one FP64 atomic each);
+//   2. the window applied to the three derivative maps, giving
+//      dSSIM/dx_p = w*dS/dmx + 2 x_p w*dS/dsxx + y_p w*dS/dsxy, and the
+//      gradient of the weighted loss.
+// A last kernel turns the sums into the per-camera loss.  The derivative maps
+// (72 bytes per pixel) and the sums (24 bytes per camera) live in the
+// caller's workspace.
+#include <string.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace lsplat {
+
+namespace {
+
+constexpr int kLTX = 32, kLTY = 16, kHalo = 5, kWin = 11;
+constexpr int kLX = kLTX + 2 * kHalo, kLY = kLTY + 2 * kHalo;   // 42 x 26 staged
+constexpr double kC1 = 0.0001, kC2 = 0.0009;
+constexpr double kWL1 = 0.6, kWL2 = 0.2, kWSSIM = 0.2;
+
+// the normalised 1D window, built by the first kWin threads
+__device__ __forceinline__ void window_1d(double* g) {
+  const int t = threadIdx.x;
+  if (t < kWin) {
+    double s = 0.0;
+    for (int k = 0; k < kWin; ++k) s += exp(-(double)((k - kHalo) * (k - kHalo)) / 4.5);
+    g[t] = exp(-(double)((t - kHalo) * (t - kHalo)) / 4.5) / s;
+  }
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Cameras of one launch: each block finds its camera from the prefix of tile
+// counts (at most kLossCams entries, uniform across the block).
+constexpr int kLossCams = 16;
+struct LossArgs {
+  int32_t count;                  // cameras in this launch
+  int32_t cam0;                   // global index of the first one
+  int32_t W[kLossCams], H[kLossCams], GX[kLossCams];
+  int32_t blk[kLossCams + 1];     // first tile block of each camera
+  int64_t pix[kLossCams];         // first pixel of each camera
+};
+
+struct LossTile {
+  int k, W, H, x0, y0;
+  int64_t plane, base;            // channel plane, offset of the camera's image
+};
+
+__device__ __forceinline__ LossTile loss_tile(const LossArgs& a) {
+  const int b = blockIdx.x;
+  int k = 0;
+  while (k + 1 < a.count && b >= a.blk[k + 1]) ++k;
+  LossTile t;
+  t.k = k;
+  t.W = a.W[k];
+  t.H = a.H[k];
+  const int lb = b - a.blk[k];
+  t.x0 = (lb % a.GX[k]) * kLTX;
+  t.y0 = (lb / a.GX[k]) * kLTY;
+  t.plane = (int64_t)t.W * t.H;
+  t.base = 3 * a.pix[k] + blockIdx.y * t.plane;
+  return t;
+}
+
+// pass 1: one (camera, 32 x 16 tile, channel) per block of 256 threads
+__global__ __launch_bounds__(256) void ssim_moments_kernel(
+    LossArgs a, const float* __restrict__ img, const float* __restrict__ tgt,
+    double* __restrict__ coef, double* __restrict__ acc) {
+  __shared__ double sx[kLY][kLX + 1], sy[kLY][kLX + 1];
+  __shared__ double hm[5][kLY][kLTX];
+  __shared__ double g[kWin];
+  __shared__ double red[3][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const LossTile t = loss_tile(a);
+  const int W = t.W, H = t.H, x0 = t.x0, y0 = t.y0;
+  const float* xi = img + t.base;
+  const float* yi = tgt + t.base;
+  // the derivative maps follow the image layout, three maps per channel
+  double* cm = coef + 3 * t.base;
+  window_1d(g);
+  for (int i = tid; i < kLY * kLX; i += 256) {
+    const int r = i / kLX, c = i % kLX;
+    const int gy = y0 - kHalo + r, gx = x0 - kHalo + c;
+    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+    const int64_t o = (int64_t)gy * W + gx;
+    sx[r][c] = in ? (double)xi[o] : 0.0;
+    sy[r][c] = in ? (double)yi[o] : 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < kLY * kLTX; i += 256) {
+    const int r = i / kLTX, c = i % kLTX;
+    double mx = 0, my = 0, xx = 0, yy = 0, xy = 0;
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      const double u = sx[r][c + k], v = sy[r][c + k], w = g[k];
+      mx = fma(w, u, mx);
+      my = fma(w, v, my);
+      xx = fma(w, u * u, xx);
+      yy = fma(w, v * v, yy);
+      xy = fma(w, u * v, xy);
+    }
+    hm[0][r][c] = mx; hm[1][r][c] = my; hm[2][r][c] = xx; hm[3][r][c] = yy; hm[4][r][c] = xy;
+  }
+  __syncthreads();
+  double ss = 0.0, s1 = 0.0, s2 = 0.0;
+  const int c = tid % kLTX;
+  for (int r = tid / kLTX; r < kLTY; r += 256 / kLTX) {
+    const int px = x0 + c, py = y0 + r;
+    double m[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kWin; ++k)
+#pragma unroll
+      for (int f = 0; f < 5; ++f) m[f] = fma(g[k], hm[f][r + k][c], m[f]);
+    if (px < W && py < H) {
+      const double mx = m[0], my = m[1];
+      const double a1 = 2.0 * mx * my + kC1;
+      const double a2 = 2.0 * (m[4] - mx * my) + kC2;
+      const double b1 = mx * mx + my * my + kC1;
+      const double b2 = (m[2] - mx * mx) + (m[3] - my * my) + kC2;
+      const double d = b1 * b2;
+      const double S = a1 * a2 / d;
+      const int64_t o = (int64_t)py * W + px;
+      cm[o] = (2.0 * my * (a2 - a1) - 2.0 * mx * S * (b2 - b1)) / d;
+      cm[t.plane + o] = -S / b2;
+      cm[2 * t.plane + o] = 2.0 * a1 / d;
+      const double df = sx[r + kHalo][c + kHalo] - sy[r + kHalo][c + kHalo];
+      ss += S;
+      s1 += fabs(df);
+      s2 += df * df;
+    }
+  }
+  ss = wave_sum_d(ss);
+  s1 = wave_sum_d(s1);
+  s2 = wave_sum_d(s2);
+  if (lane == 0) {
+    red[0][wave] = ss;
+    red[1][wave] = s1;
+    red[2][wave] = s2;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    // sums enter already divided by the camera's 3 H W values
+    const double inv_n = 1.0 / (3.0 * (double)t.plane);
+    const double v = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+    atomicAdd(acc + 3 * (a.cam0 + t.k) + tid, v * inv_n);
+  }
+}
+
+// pass 2: the window over the derivative maps, then the gradient
+__global__ __launch_bounds__(256) void ssim_grad_kernel(
+    LossArgs a, const float* __restrict__ img, const float* __restrict__ tgt,
+    const double* __restrict__ coef, float* __restrict__ grad) {
+  __shared__ double sc[3][kLY][kLX + 1];
+  __shared__ double hb[3][kLY][kLTX];
+  __shared__ double g[kWin];
+  const int tid = threadIdx.x;
+  const LossTile t = loss_tile(a);
+  const int W = t.W, H = t.H, x0 = t.x0, y0 = t.y0;
+  const double* cm = coef + 3 * t.base;
+  const double inv_n = 1.0 / (3.0 * (double)t.plane);
+  window_1d(g);
+  for (int i = tid; i < kLY * kLX; i += 256) {
+    const int r = i / kLX, c = i % kLX;
+    const int gy = y0 - kHalo + r, gx = x0 - kHalo + c;
+    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+    const int64_t o = (int64_t)gy * W + gx;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) sc[f][r][c] = in ? cm[f * t.plane + o] : 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < kLY * kLTX; i += 256) {
+    const int r = i / kLTX, c = i % kLTX;
+    double v[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kWin; ++k)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) v[f] = fma(g[k], sc[f][r][c + k], v[f]);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) hb[f][r][c] = v[f];
+  }
+  __syncthreads();
+  const int c = tid % kLTX;
+  for (int r = tid / kLTX; r < kLTY; r += 256 / kLTX) {
+    const int px = x0 + c, py = y0 + r;
+    if (px >= W || py >= H) continue;
+    double v[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kWin; ++k)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) v[f] = fma(g[k], hb[f][r + k][c], v[f]);
+    const int64_t o = t.base + (int64_t)py * W + px;
+    const double x = (double)img[o], y = (double)tgt[o];
+    const double df = x - y;
+    const double sg = df > 0.0 ? 1.0 : (df < 0.0 ? -1.0 : 0.0);
+    const double dssim = v[0] + 2.0 * x * v[1] + y * v[2];
+    grad[o] = (float)((kWL1 * sg + kWL2 * 2.0 * df - kWSSIM * dssim) * inv_n);
+  }
+}
+
+__global__ void loss_zero_kernel(double* __restrict__ acc, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) acc[i] = 0.0;
+}
+
+__global__ void loss_finalize_kernel(const double* __restrict__ acc, int C,
+                                     double* __restrict__ loss) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < C) loss[c] = kWL1 * acc[3 * c + 1] + kWL2 * acc[3 * c + 2] + kWSSIM * (1.0 - acc[3 * c]);
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t loss_workspace_bytes(int64_t P, int C) {
+  // FP64 derivative maps (3 per channel and pixel), then the per-camera sums
+  return align256((size_t)P * 72) + align256((size_t)C * 24);
+}
+
+hipError_t launch_loss(const int32_t* W, const int32_t* H, int C, const float* image,
+                       const float* target, float* dL_dimage, double* loss, char* ws,
+                       hipStream_t s) {
+  int64_t P = 0;
+  for (int c = 0; c < C; ++c) P += (int64_t)W[c] * H[c];
+  double* coef = (double*)ws;
+  double* acc = (double*)(ws + align256((size_t)P * 72));
+  hipError_t e;
+  ProfScope ps("loss", s);
+  hipLaunchKernelGGL(loss_zero_kernel, dim3((3 * C + 255) / 256), dim3(256), 0, s, acc, 3 * C);
+  if ((e = hipGetLastError())) return e;
+  int64_t pix = 0;
+  for (int first = 0; first < C; first += kLossCams) {
+    LossArgs a;
+    memset(&a, 0, sizeof(a));
+    a.cam0 = first;
+    a.count = std::min(kLossCams, C - first);
+    a.blk[0] = 0;
+    for (int k = 0; k < a.count; ++k) {
+      const int c = first + k;
+      a.W[k] = W[c];
+      a.H[k] = H[c];
+      a.GX[k] = (W[c] + kLTX - 1) / kLTX;
+      a.blk[k + 1] = a.blk[k] + a.GX[k] * ((H[c] + kLTY - 1) / kLTY);
+      a.pix[k] = pix;
+      pix += (int64_t)W[c] * H[c];
+    }
+    const dim3 grid((unsigned)a.blk[a.count], 3);
+    hipLaunchKernelGGL(ssim_moments_kernel, grid, dim3(256), 0, s, a, image, target, coef, acc);
+    hipLaunchKernelGGL(ssim_grad_kernel, grid, dim3(256), 0, s, a, image, target, coef, dL_dimage);
+    if ((e = hipGetLastError())) return e;
+  }
+  hipLaunchKernelGGL(loss_finalize_kernel, dim3((C + 255) / 256), dim3(256), 0, s, acc, C, loss);
+  return hipGetLastError();
+}
+
+}  // namespace lsplat

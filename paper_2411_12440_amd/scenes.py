@@ -187,6 +187,33 @@ def upstream_grad(cams: Cameras, seed: int) -> np.ndarray:
     return g.normal(0.0, 1.0, size=total).astype(np.float32)
 
 
+def image_pair(widths, heights, seed: int, noise: float | None = 0.1):
+    """A rendered image and its target photograph for the training loss,
+    float32, planar per camera like ``upstream_grad``.  Per camera and
+    channel the target is 0.5 + 0.25 sin(a x + b y + phi) (a, b ~ U[-0.3, 0.3],
+    phi ~ U[0, 2 pi]) plus U[-0.25, 0.25] texture; the render is the target
+    plus N(0, noise), clipped to [0, 1].  noise=None: both images are
+    independent U[0, 1] (no structure shared)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    imgs, tgts = [], []
+    for w, h in zip(widths, heights):
+        w, h = int(w), int(h)
+        if noise is None:
+            imgs.append(g.uniform(0.0, 1.0, 3 * w * h))
+            tgts.append(g.uniform(0.0, 1.0, 3 * w * h))
+            continue
+        yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+        t = np.empty((3, h, w))
+        for ch in range(3):
+            a, b = g.uniform(-0.3, 0.3, 2)
+            phi = g.uniform(0.0, 2.0 * math.pi)
+            t[ch] = 0.5 + 0.25 * np.sin(a * xx + b * yy + phi) + g.uniform(-0.25, 0.25, (h, w))
+        r = np.clip(t + g.normal(0.0, noise, t.shape), 0.0, 1.0)
+        imgs.append(r.ravel())
+        tgts.append(t.ravel())
+    return (np.concatenate(imgs).astype(np.float32), np.concatenate(tgts).astype(np.float32))
+
+
 # ---------------------------------------------------------------------------
 # The five workloads.  Seeds: scene k -> 1000 + k, extra scene s -> 5000 + s,
 # upstream gradient -> 7000 + k, resolution permutation -> 9000 + k.

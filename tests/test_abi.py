@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(B.EXPORTS) == set(declared_functions())
-    assert B.ls_version() == 130
+    assert B.ls_version() == 140
 
 
 def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):
@@ -128,3 +128,22 @@ def test_depth_chunks_layout():
     T = 8 * 6
     assert l6.n_isect - l6.ranges >= 8 * 6 * (T + 1)
     assert l6.total_bytes > l1.total_bytes + 32 * 128 * 96
+
+
+def test_loss_arguments_checked():
+    """ls_loss validates cameras, pointers and workspace before launching."""
+    from paper_2411_12440_amd import binding as B
+    lib = B.LIB
+    cams = _cams(w=(40, 7), h=(30, 5), scene=(0, 0))
+    n = B.ls_loss_workspace_size(cams)
+    assert n >= 72 * (40 * 30 + 7 * 5) + 48
+    with pytest.raises(B.LsError):
+        B.ls_loss_workspace_size(_cams(w=(0,)))
+    ws = C.create_string_buffer(n + 512)
+    base = (C.addressof(ws) + 255) // 256 * 256
+    one = C.c_void_p(8)
+    assert lib.ls_loss(C.byref(cams.c), None, one, one, one, base, n, None) == -1
+    assert lib.ls_loss(C.byref(cams.c), one, one, one, one, None, n, None) == -5
+    assert lib.ls_loss(C.byref(cams.c), one, one, one, one, base + 8, n, None) == -5
+    assert lib.ls_loss(C.byref(cams.c), one, one, one, one, base, n - 1, None) == -5
+    assert b"loss needs" in lib.ls_last_error()

@@ -78,3 +78,16 @@ def test_gradient_against_finite_differences(seed):
         xm[idx] -= h
         fd[idx] = (loss.loss_one(xp, y)[0] - loss.loss_one(xm, y)[0]) / (2 * h)
     assert np.abs(fd - g).max() < 1e-8 * max(1.0, np.abs(g).max()) + 1e-9
+
+
+def test_crop_gradient_is_exact():
+    """The full-size GPU test samples the oracle's gradient through crops
+    reaching two window radii around a pixel; on a small image that agrees
+    with the whole-image gradient, at the border as well as inside."""
+    from tests.test_gpu_loss import _crop_grad
+    rng = np.random.default_rng(4)
+    x, y = rng.uniform(0, 1, (3, 40, 57)), rng.uniform(0, 1, (3, 40, 57))
+    _, g, _ = loss.loss_one(x, y)
+    for py, px in [(0, 0), (39, 56), (20, 30), (3, 50), (12, 11)]:
+        np.testing.assert_allclose(_crop_grad(x, y, py, px, x.size), g[:, py, px],
+                                   rtol=1e-12, atol=1e-18)
