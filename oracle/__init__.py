@@ -27,6 +27,9 @@ Every function here is plain and slow on purpose.  Modules:
   render      whole-path driver over cameras and scenes
   loss        the training loss (L1, L2, SSIM; implementation section) and its
               gradient with respect to the rendered image
+  adam        one Adam step (FP64)
+  densify     densification statistics and the grow / prune decision with
+              the 3DLS thresholds
 """
 from .config import RasterConfig  # noqa: F401
 from .render import render_forward, render_backward  # noqa: F401
