@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 140
+#define LSPLAT_VERSION 150
 
 typedef enum {
   LS_OK = 0,
@@ -343,6 +343,93 @@ ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* splats,
 ls_status ls_loss_workspace_size(const ls_cameras* cams, size_t* bytes);
 ls_status ls_loss(const ls_cameras* cams, const float* image, const float* target,
                   float* dL_dimage, double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adam (Kingma and Ba 2015), the optimiser of the 3DGS training the paper
+ * keeps.  One step t >= 1 over n parameters, per element:
+ *   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+ *   param <- param - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ * The arithmetic is FP64 on the FP32 arrays (one rounding per stored value).
+ * Call once per parameter group (each has its own learning rate).  The
+ * 3DGS lineage uses beta1 = 0.9, beta2 = 0.999, eps = 1e-15.
+ * param, m, v  [n] device, updated in place; m and v start at zero.
+ * grad         [n] device.
+ * Checks: n >= 0, step >= 1, 0 <= beta1, beta2 < 1, eps >= 0, non-NULL
+ * pointers when n > 0.  Allocates nothing.
+ */
+typedef struct ls_adam_params {
+  double lr;
+  double beta1;
+  double beta2;
+  double eps;
+  int64_t step;
+} ls_adam_params;
+
+ls_status ls_adam(const ls_adam_params* prm, int64_t n, float* param, const float* grad,
+                  float* m, float* v, void* stream);
+
+/*
+ * Densification statistics (the per-splat quantities 3DGS adaptive density
+ * control accumulates between densification steps; the paper's
+ * densification table gives 3DLS thresholds for the decision below).
+ * Accumulators, per splat, [n] device, zeroed by the caller when a new
+ * accumulation period starts:
+ *   grad        sum over visible pairs of |(dL/dx W/2, dL/dy H/2)|, the norm
+ *               of the projected centre's gradient in normalised device
+ *               coordinates.
+ *   count       number of visible pairs (support on at least one tile).
+ *   max_extent  max over visible pairs of the support ellipse's semi-major
+ *               axis in pixels (extent times the square root of the largest
+ *               eigenvalue of the dilated 2D covariance) over max(W, H).
+ */
+typedef struct ls_densify_acc {
+  float* grad;
+  int32_t* count;
+  float* max_extent;
+} ls_densify_acc;
+
+/*
+ * Adds the statistics of the backward pass that last ran on `ws` (same
+ * settings, cameras and capacity as that ls_rasterize_bwd call).  Reads the
+ * projection records and per-pair gradients the pass left in the workspace.
+ */
+ls_status ls_densify_stats(const ls_config* cfg, const ls_cameras* cams, void* ws,
+                           size_t ws_bytes, int64_t isect_capacity, const ls_densify_acc* acc,
+                           void* stream);
+
+/*
+ * The grow / prune decision.  With s the largest of a splat's three scales:
+ *   high      = count > 0 and grad / count > grad_threshold
+ *   small     = s <= grow_scale3d * scene_scale
+ *   split     = (high and not small) or (grow2d and max_extent > grow_scale2d)
+ *   duplicate = high and small and not split
+ *   prune     = opacity < prune_opacity, or (prune_big and (s > prune_scale3d
+ *               * scene_scale or max_extent > prune_scale2d))
+ * compared in FP64 on the stored values.  3DLS thresholds (paper table):
+ * 0.0002, 0.05, 0.006, 0.15, 0.4, 0.025 in the order of the fields below;
+ * 3DGS: 0.0002, 0.05, 0.01, 0.15, 0.1, 0.005.  grow2d and prune_big switch
+ * the screen-size and large-splat rules on (the schedule's choice).
+ * scales   [3][n], opacity [n] as in ls_splats.
+ * action   [n] device out: bit 1 duplicate, 2 split, 4 prune.
+ * counts   optional [3] device out (NULL to skip): splats to duplicate, to
+ *          split and to prune.
+ * Applying the decision (new splats, compaction) is the training loop's.
+ */
+typedef struct ls_densify_params {
+  double grad_threshold;
+  double grow_scale2d;
+  double grow_scale3d;
+  double prune_scale2d;
+  double prune_scale3d;
+  double prune_opacity;
+  double scene_scale;
+  int32_t grow2d;
+  int32_t prune_big;
+} ls_densify_params;
+
+ls_status ls_densify_select(const ls_densify_params* prm, int64_t n, const float* scales,
+                            const float* opacity, const ls_densify_acc* acc, uint8_t* action,
+                            int64_t* counts, void* stream);
 
 /*
  * Kernel timing (tracing).  While enabled, every kernel the library enqueues

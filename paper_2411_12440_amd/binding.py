@@ -65,6 +65,22 @@ class Layout(C.Structure):
                 ("tile_contrib", C.c_size_t), ("scratch", C.c_size_t)]
 
 
+class AdamParams(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("step", C.c_int64)]
+
+
+class DensifyAcc(C.Structure):
+    _fields_ = [("grad", C.c_void_p), ("count", C.c_void_p), ("max_extent", C.c_void_p)]
+
+
+class DensifyParams(C.Structure):
+    _fields_ = [("grad_threshold", C.c_double), ("grow_scale2d", C.c_double),
+                ("grow_scale3d", C.c_double), ("prune_scale2d", C.c_double),
+                ("prune_scale3d", C.c_double), ("prune_opacity", C.c_double),
+                ("scene_scale", C.c_double), ("grow2d", C.c_int32), ("prune_big", C.c_int32)]
+
+
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -92,6 +108,12 @@ def _load() -> C.CDLL:
         "ls_loss_workspace_size": ([P(Cams), P(C.c_size_t)], C.c_int),
         "ls_loss": ([P(Cams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
+        "ls_adam": ([P(AdamParams), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.c_void_p], C.c_int),
+        "ls_densify_stats": ([P(Config), P(Cams), C.c_void_p, C.c_size_t, C.c_int64,
+                              P(DensifyAcc), C.c_void_p], C.c_int),
+        "ls_densify_select": ([P(DensifyParams), C.c_int64, C.c_void_p, C.c_void_p,
+                               P(DensifyAcc), C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
         "ls_profile_enable": ([C.c_int], C.c_int),
         "ls_profile_read": ([P(KernelTime), C.c_int, P(C.c_int), C.c_int], C.c_int),
     }
@@ -105,7 +127,8 @@ def _load() -> C.CDLL:
 LIB = _load()
 EXPORTS = ("ls_version", "ls_last_error", "ls_workspace_size", "ls_workspace_layout",
            "ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd",
-           "ls_loss_workspace_size", "ls_loss", "ls_profile_enable", "ls_profile_read")
+           "ls_loss_workspace_size", "ls_loss", "ls_adam", "ls_densify_stats",
+           "ls_densify_select", "ls_profile_enable", "ls_profile_read")
 
 
 def _check(st: int):
@@ -210,6 +233,41 @@ def ls_loss_workspace_size(cams: CamerasHost) -> int:
 def ls_loss(cams: CamerasHost, image, target, dL_dimage, loss, ws, stream=None):
     _check(LIB.ls_loss(C.byref(cams.c), _ptr(image), _ptr(target), _ptr(dL_dimage), _ptr(loss),
                        _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def adam_params(lr, step, beta1=0.9, beta2=0.999, eps=1e-15) -> AdamParams:
+    return AdamParams(lr, beta1, beta2, eps, step)
+
+
+def ls_adam(prm: AdamParams, param, grad, m, v, stream=None):
+    _check(LIB.ls_adam(C.byref(prm), param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
+                       _stream(stream)))
+
+
+def densify_acc(grad, count, max_extent) -> DensifyAcc:
+    return DensifyAcc(_ptr(grad), _ptr(count), _ptr(max_extent))
+
+
+# thresholds of the paper's densification table, in the order of the
+# DensifyParams fields: gradient, 2D grow, 3D grow, 2D prune, 3D prune, opacity
+THRESH_3DLS = (0.0002, 0.05, 0.006, 0.15, 0.4, 0.025)
+THRESH_3DGS = (0.0002, 0.05, 0.01, 0.15, 0.1, 0.005)
+
+
+def densify_params(scene_scale, thresholds=THRESH_3DLS, grow2d=False,
+                   prune_big=False) -> DensifyParams:
+    return DensifyParams(*thresholds, scene_scale, int(grow2d), int(prune_big))
+
+
+def ls_densify_stats(cfg, cams: CamerasHost, ws, capacity, acc: DensifyAcc, stream=None):
+    _check(LIB.ls_densify_stats(C.byref(cfg), C.byref(cams.c), _ptr(ws), ws.numel(), capacity,
+                                C.byref(acc), _stream(stream)))
+
+
+def ls_densify_select(prm: DensifyParams, n, scales, opacity, acc: DensifyAcc, action,
+                      counts=None, stream=None):
+    _check(LIB.ls_densify_select(C.byref(prm), n, _ptr(scales), _ptr(opacity), C.byref(acc),
+                                 _ptr(action), _ptr(counts), _stream(stream)))
 
 
 def ls_profile_enable(on: bool = True):

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblsplat.so")
-SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "loss.hip", "profile.hip"]
+SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "loss.hip", "train.hip", "profile.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

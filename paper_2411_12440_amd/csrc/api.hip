@@ -1,6 +1,6 @@
 // C-ABI entry points of liblsplat: argument validation, workspace planning and
 // the enqueue of each stage.  Kernels live in project.hip, binsort.hip,
-// raster.hip and (the training loss) loss.hip.
+// raster.hip, and (training-step stages) loss.hip and train.hip.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -325,6 +325,55 @@ ls_status ls_loss(const ls_cameras* cams, const float* image, const float* targe
   hipError_t e = launch_loss(cams->h_width, cams->h_height, cams->n_cams, image, target, dL_dimage,
                              loss, (char*)ws, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "loss");
+  return LS_OK;
+}
+
+ls_status ls_adam(const ls_adam_params* prm, int64_t n, float* param, const float* grad,
+                  float* m, float* v, void* stream) {
+  if (!prm) return fail(LS_ERR_INVALID_ARG, "prm is NULL");
+  if (n < 0) return fail(LS_ERR_INVALID_ARG, "n must be >= 0");
+  if (prm->step < 1) return fail(LS_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(prm->beta1 >= 0.0 && prm->beta1 < 1.0) || !(prm->beta2 >= 0.0 && prm->beta2 < 1.0))
+    return fail(LS_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
+  if (!(prm->eps >= 0.0) || !(prm->lr == prm->lr)) return fail(LS_ERR_INVALID_ARG, "eps must be >= 0, lr finite");
+  if (n > 0 && (!param || !grad || !m || !v)) return fail(LS_ERR_INVALID_ARG, "param/grad/m/v is NULL");
+  hipError_t e = launch_adam(prm, n, param, grad, m, v, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "adam");
+  return LS_OK;
+}
+
+ls_status ls_densify_stats(const ls_config* cfg, const ls_cameras* cams, void* ws,
+                           size_t ws_bytes, int64_t cap, const ls_densify_acc* acc,
+                           void* stream) {
+  Plan p;
+  ls_status st = make_plan(cfg, cams, cap, &p);
+  if (st != LS_OK) return st;
+  if ((st = check_ws(p, ws, ws_bytes)) != LS_OK) return st;
+  if (!acc || (p.N > 0 && (!acc->grad || !acc->count || !acc->max_extent)))
+    return fail(LS_ERR_INVALID_ARG, "accumulator pointer is NULL");
+  hipError_t e = launch_densify_stats(p, cfg, (char*)ws, acc, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "densify_stats");
+  return LS_OK;
+}
+
+ls_status ls_densify_select(const ls_densify_params* prm, int64_t n, const float* scales,
+                            const float* opacity, const ls_densify_acc* acc, uint8_t* action,
+                            int64_t* counts, void* stream) {
+  if (!prm) return fail(LS_ERR_INVALID_ARG, "prm is NULL");
+  if (n < 0) return fail(LS_ERR_INVALID_ARG, "n must be >= 0");
+  const double th[7] = {prm->grad_threshold, prm->grow_scale2d, prm->grow_scale3d,
+                        prm->prune_scale2d, prm->prune_scale3d, prm->prune_opacity,
+                        prm->scene_scale};
+  for (double t : th)
+    if (!(t >= 0.0) || !(t < 1e300)) return fail(LS_ERR_INVALID_ARG, "thresholds must be finite and >= 0");
+  if ((prm->grow2d != 0 && prm->grow2d != 1) || (prm->prune_big != 0 && prm->prune_big != 1))
+    return fail(LS_ERR_INVALID_ARG, "grow2d and prune_big must be 0 or 1");
+  if (n > 0 && (!scales || !opacity || !action || !acc || !acc->grad || !acc->count ||
+                !acc->max_extent))
+    return fail(LS_ERR_INVALID_ARG, "scales/opacity/action/accumulator pointer is NULL");
+  hipError_t e = launch_densify_select(prm, n, scales, opacity, acc, action, counts,
+                                       (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "densify_select");
   return LS_OK;
 }
 

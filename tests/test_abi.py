@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(B.EXPORTS) == set(declared_functions())
-    assert B.ls_version() == 140
+    assert B.ls_version() == 150
 
 
 def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):
@@ -147,3 +147,28 @@ def test_loss_arguments_checked():
     assert lib.ls_loss(C.byref(cams.c), one, one, one, one, base + 8, n, None) == -5
     assert lib.ls_loss(C.byref(cams.c), one, one, one, one, base, n - 1, None) == -5
     assert b"loss needs" in lib.ls_last_error()
+
+
+def test_training_stage_arguments_checked():
+    """ls_adam and ls_densify_select validate before launching anything."""
+    from paper_2411_12440_amd import binding as B
+    lib = B.LIB
+    one = C.c_void_p(8)
+    bad = [B.adam_params(0.1, 0), B.adam_params(0.1, 1, beta1=1.0), B.adam_params(0.1, 1, eps=-1.0),
+           B.adam_params(float("nan"), 1)]
+    for prm in bad:
+        assert lib.ls_adam(C.byref(prm), 4, one, one, one, one, None) == -1
+    assert lib.ls_adam(C.byref(B.adam_params(0.1, 1)), -1, one, one, one, one, None) == -1
+    assert lib.ls_adam(C.byref(B.adam_params(0.1, 1)), 4, None, one, one, one, None) == -1
+    acc = B.DensifyAcc(8, 8, 8)
+    prm = B.densify_params(1.0)
+    prm.grow2d = 2
+    assert lib.ls_densify_select(C.byref(prm), 4, one, one, C.byref(acc), one, None, None) == -1
+    prm = B.densify_params(-1.0)
+    assert lib.ls_densify_select(C.byref(prm), 4, one, one, C.byref(acc), one, None, None) == -1
+    prm = B.densify_params(1.0)
+    assert lib.ls_densify_select(C.byref(prm), 4, one, None, C.byref(acc), one, None, None) == -1
+    cfg = B.make_config()
+    cams = _cams()
+    assert lib.ls_densify_stats(C.byref(cfg), C.byref(cams.c), None, 0, 0, C.byref(acc),
+                                None) == -5

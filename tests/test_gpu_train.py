@@ -1,0 +1,220 @@
+"""GPU parity of the training-step stages around the rasterizer, through the
+C ABI: the Adam step (ls_adam) and the densification statistics and decision
+(ls_densify_stats, ls_densify_select), against the FP64 oracles in
+oracle/adam.py and oracle/densify.py on the same seeded inputs.
+
+Bars: Adam computes in FP64 and rounds each stored value once, so every
+output is within 1 FP32 ulp of the oracle's FP64 value.  The decision is an
+integer taken in FP64 on the same stored FP32 values on both sides: bit-exact.
+The statistics: view counts bit-exact (the visibility comes from the bit-exact
+binning), the support extent within 2 FP32 ulp, the gradient norm sums at the
+rasterizer's gradient bar (1e-5 relative, from the per-pair gradients)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import adam as oadam
+from oracle import densify as odens
+from oracle import render_backward, render_forward
+from oracle.config import extent
+from paper_2411_12440_amd import scenes
+from tests.gpu_helpers import assert_close, cfg_pair, gpu_forward, pixel_flags_to_image, say
+
+pytestmark = pytest.mark.gpu
+
+ULP = 2.0 ** -23
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _within_ulp(got, ref, ulps, what):
+    got = np.asarray(got, np.float64)
+    err = np.abs(got - ref)
+    bound = ulps * ULP * np.abs(ref) + 1e-38
+    bad = err > bound
+    assert not bad.any(), (f"{what}: {int(bad.sum())} of {bad.size} off, worst rel "
+                           f"{(err / np.maximum(np.abs(ref), 1e-38)).max():.3e}")
+
+
+# ---------------------------------------------------------------------------
+# Adam
+# ---------------------------------------------------------------------------
+
+def _adam_inputs(n, t, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    p = g.normal(0.0, 1.0, n)
+    grad = g.normal(0.0, 1.0, n) * 10.0 ** g.uniform(-6, 2, n)
+    grad[::17] = 0.0
+    if t == 1:
+        m = np.zeros(n)
+        v = np.zeros(n)
+    else:
+        m = g.normal(0.0, 0.1, n)
+        v = np.abs(g.normal(0.0, 1.0, n)) * 10.0 ** g.uniform(-8, 0, n)
+    return [a.astype(np.float32) for a in (p, grad, m, v)]
+
+
+@pytest.mark.parametrize("n,t,offset", [(1, 1, 0), (7, 1, 0), (1000, 2, 0), (1000003, 50, 0),
+                                        (4099, 3, 1), (65536, 1000, 0)])
+def test_adam_step(n, t, offset):
+    """offset 1 starts every array one element into its buffer, which takes
+    the unaligned path; odd sizes leave a tail after the 4-wide part."""
+    import torch
+    from paper_2411_12440_amd import binding as B
+    say(f"adam: n={n} t={t} offset={offset}")
+    p, g, m, v = _adam_inputs(n, t, 100 + t)
+    dev = [torch.from_numpy(np.concatenate([np.zeros(offset, np.float32), a])).cuda()[offset:]
+           for a in (p, g, m, v)]
+    lr = 1.6e-4 if t < 100 else 0.05
+    B.ls_adam(B.adam_params(lr, t), *dev)
+    torch.cuda.synchronize()
+    po, mo, vo = oadam.step(p, g, m, v, t, lr)
+    _within_ulp(dev[0].cpu().numpy(), po, 1, "param")
+    _within_ulp(dev[2].cpu().numpy(), mo, 1, "m")
+    _within_ulp(dev[3].cpu().numpy(), vo, 1, "v")
+    assert np.array_equal(dev[1].cpu().numpy(), g)
+
+
+def test_adam_steps_in_sequence():
+    """Five steps, each from the state the previous GPU step stored (the
+    oracle step takes the same FP32 state)."""
+    import torch
+    from paper_2411_12440_amd import binding as B
+    n = 5000
+    p, _, m, v = _adam_inputs(n, 1, 7)
+    dev = [torch.from_numpy(a).cuda() for a in (p, m, v)]
+    rng = np.random.Generator(np.random.PCG64(8))
+    for t in range(1, 6):
+        g = (rng.normal(0.0, 1.0, n) * 1e-3).astype(np.float32)
+        state = [d.cpu().numpy() for d in dev]
+        gd = torch.from_numpy(g).cuda()
+        B.ls_adam(B.adam_params(0.01, t), dev[0], gd, dev[1], dev[2])
+        torch.cuda.synchronize()
+        po, mo, vo = oadam.step(state[0], g, state[1], state[2], t, 0.01)
+        _within_ulp(dev[0].cpu().numpy(), po, 1, f"param step {t}")
+        _within_ulp(dev[1].cpu().numpy(), mo, 1, f"m step {t}")
+        _within_ulp(dev[2].cpu().numpy(), vo, 1, f"v step {t}")
+
+
+# ---------------------------------------------------------------------------
+# densification decision
+# ---------------------------------------------------------------------------
+
+def _select_inputs(n, seed, scene_scale):
+    g = np.random.Generator(np.random.PCG64(seed))
+    count = g.integers(0, 6, n).astype(np.int32)
+    grad = (count * 2e-4 * g.uniform(0.5, 1.5, n)).astype(np.float32)
+    scales = (np.exp(g.normal(-5.0, 1.5, (3, n))) * scene_scale).astype(np.float32)
+    opac = g.uniform(0.0, 0.2, n).astype(np.float32)
+    ext = g.uniform(0.0, 0.3, n).astype(np.float32)
+    # values on the thresholds themselves (as stored in FP32)
+    k = n // 10
+    opac[:k] = np.float32(0.025)
+    ext[k:2 * k] = np.float32(0.05)
+    ext[2 * k:3 * k] = np.float32(0.15)
+    scales[1, 3 * k:4 * k] = np.float32(0.006 * scene_scale)
+    count[4 * k:5 * k] = 1
+    grad[4 * k:5 * k] = np.float32(2e-4)
+    return grad, count, ext, scales, opac
+
+
+@pytest.mark.parametrize("thresholds", ["3dls", "3dgs"])
+@pytest.mark.parametrize("grow2d,prune_big", [(False, False), (True, True), (True, False)])
+def test_densify_select(thresholds, grow2d, prune_big):
+    import torch
+    from paper_2411_12440_amd import binding as B
+    n, S = 30011, 3.7
+    say(f"densify select: {thresholds} grow2d={grow2d} prune_big={prune_big} n={n}")
+    grad, count, ext, scales, opac = _select_inputs(n, 55, S)
+    th_c = B.THRESH_3DLS if thresholds == "3dls" else B.THRESH_3DGS
+    th_o = odens.THRESH_3DLS if thresholds == "3dls" else odens.THRESH_3DGS
+    d = {k: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+         for k, a in dict(grad=grad, count=count, ext=ext, scales=scales, opac=opac).items()}
+    action = torch.full((n,), 255, dtype=torch.uint8, device="cuda")
+    counts = torch.full((3,), -1, dtype=torch.int64, device="cuda")
+    acc = B.densify_acc(d["grad"], d["count"], d["ext"])
+    B.ls_densify_select(B.densify_params(S, th_c, grow2d, prune_big), n, d["scales"], d["opac"],
+                        acc, action, counts)
+    torch.cuda.synchronize()
+    want = odens.select(dict(grad=grad.astype(np.float64), count=count,
+                             max_extent=ext.astype(np.float64)),
+                        scales.T.astype(np.float64), opac.astype(np.float64), S, th_o,
+                        grow2d=grow2d, prune_big=prune_big)
+    got = action.cpu().numpy()
+    assert np.array_equal(got, want), f"{int((got != want).sum())} decisions differ"
+    c = counts.cpu().numpy()
+    assert c.tolist() == [int(((want >> b) & 1).sum()) for b in range(3)]
+    assert len(set(want.tolist())) >= 4
+
+
+def test_densify_select_empty():
+    import torch
+    from paper_2411_12440_amd import binding as B
+    counts = torch.full((3,), -1, dtype=torch.int64, device="cuda")
+    acc = B.DensifyAcc(0, 0, 0)
+    B.ls_densify_select(B.densify_params(1.0), 0, None, None, acc, None, counts)
+    torch.cuda.synchronize()
+    assert counts.cpu().tolist() == [0, 0, 0]
+
+
+# ---------------------------------------------------------------------------
+# densification statistics
+# ---------------------------------------------------------------------------
+
+def _oracle_stats(fw, go, cams, ocfg, acc):
+    lay = fw.lay
+    sp, cp, cov = [], [], []
+    for c in range(cams.n):
+        sp.append(np.arange(int(lay.splat_lo[c]), int(lay.splat_hi[c])))
+        cp.append(np.full(int(lay.splat_hi[c] - lay.splat_lo[c]), c))
+        cov.append(fw.proj[c]["cov2d"])
+    return odens.accumulate(acc, np.concatenate(sp), np.concatenate(cp), fw.ntiles > 0,
+                            go["pair"]["mean2d"], np.concatenate(cov), cams.width, cams.height,
+                            extent(ocfg))
+
+
+@pytest.mark.parametrize("kernel,chunks", [("linear", 1), ("linear", 3), ("gaussian", 1)])
+def test_densify_stats(kernel, chunks):
+    """Three scenes, six cameras of uneven size; the statistics of one
+    backward pass added twice onto non-zero accumulators."""
+    import torch
+    from paper_2411_12440_amd import binding as B
+    say(f"densify stats: {kernel}, depth chunks {chunks}")
+    scs = [scenes.make_scene(n, 930 + i, -3.0, 0.5, 1) for i, n in enumerate((600, 1100, 300))]
+    scene, off = scenes.concat_scenes(scs)
+    res = [(96, 64), (130, 70), (64, 64), (200, 90), (50, 120), (128, 96)]
+    cams = scenes.sphere_cameras(6, 4.0, res, scene_of_cam=[0, 1, 2, 0, 1, 2])
+    lam = 2.5 if kernel == "linear" else 1.0
+    ocfg, gkw = cfg_pair(depth_chunks=chunks, kernel=kernel, lambda_=lam)
+    G = scenes.upstream_grad(cams, 7021)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    G = G * ~pixel_flags_to_image(fw.flag, cams)
+    go = render_backward(fw, scene, cams, G)
+    rast, sp = gpu_forward(scene, off, cams, gkw)
+    rast.backward(sp, torch.from_numpy(G.astype(np.float32)).cuda())
+
+    N = scene.n
+    rng = np.random.Generator(np.random.PCG64(3))
+    g0 = (rng.uniform(0, 1e-3, N)).astype(np.float32)
+    c0 = rng.integers(0, 3, N).astype(np.int32)
+    e0 = (rng.uniform(0, 0.02, N)).astype(np.float32)
+    dg, dc, de = (torch.from_numpy(a).cuda() for a in (g0, c0, e0))
+    acc = B.densify_acc(dg, dc, de)
+    for _ in range(2):
+        B.ls_densify_stats(rast.cfg, rast.cams, rast.ws, rast.capacity, acc)
+    torch.cuda.synchronize()
+    oacc = dict(grad=g0.astype(np.float64), count=c0.astype(np.int64),
+                max_extent=e0.astype(np.float64))
+    for _ in range(2):
+        _oracle_stats(fw, go, cams, ocfg, oacc)
+    got_c = dc.cpu().numpy()
+    assert np.array_equal(got_c, oacc["count"])
+    assert (got_c > c0).sum() > N // 4, "too few visible splats for a meaningful test"
+    _within_ulp(de.cpu().numpy(), oacc["max_extent"], 2, "max_extent")
+    assert_close("densify grad", dg.cpu().numpy().astype(np.float64), oacc["grad"])
