@@ -16,8 +16,12 @@ Paths timed with the same kernels:
   per-view  one view at a time, each with its own right-sized workspace and
             a host read-back of the intersection count after binning
 The JSON line also carries the per-view rate, the dominant kernel's roofline
-fraction (its algorithmic work over its average event-timed duration) and the
-FP64 oracle timed on a bounded sample on the host CPU.
+fraction (its algorithmic work over its average event-timed duration), the
+FP64 oracle timed on a bounded sample on the host CPU, and the training-step
+stages around the rasterizer on the same workload (the L1/L2/SSIM loss of
+the 8 rendered views against seeded targets, one Adam step over every splat
+parameter, the densification statistics and decision), each with its
+algorithmic HBM bytes over its event-timed duration.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -56,6 +60,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-family", action="store_true",
                     help="skip the linear vs Gaussian kernel comparison")
+    ap.add_argument("--no-train-stages", action="store_true",
+                    help="skip the loss / Adam / densification timings")
     return ap.parse_args()
 
 
@@ -185,6 +191,70 @@ def cpu_baseline(scene, cams, n_tiles_sample=6):
 
 
 # --------------------------------------------------------------------------
+
+def training_stages(B, S, torch, rast, sp, grads, cams, steps, warmup):
+    """Event-timed loss, Adam and densification calls on the step's own
+    outputs, with algorithmic bytes: loss 12 B per pixel and channel (image
+    and target read, gradient written), Adam 28 B per parameter (parameter,
+    gradient and both moments read; parameter and moments written),
+    statistics 44 B per visible-or-not pair (two FP64 gradient components,
+    the tile count, the FP64 conic) plus 24 B per splat (accumulators read
+    and written), decision 29 B per splat."""
+    dev = rast.image.device
+    N = int(sp["opacity"].numel())
+    M = int(rast.layout.n_pairs)
+    P = int(rast.layout.n_pixels)
+    _, target = S.image_pair(cams.width, cams.height, seed=7100)
+    target = torch.from_numpy(target).to(dev)
+    lws = torch.empty(B.ls_loss_workspace_size(rast.cams), dtype=torch.uint8, device=dev)
+    dimg = torch.empty_like(rast.image)
+    lossv = torch.empty(cams.n, dtype=torch.float64, device=dev)
+    state = {k: (torch.zeros_like(v), torch.zeros_like(v)) for k, v in sp.items()}
+    params = {k: v.clone() for k, v in sp.items()}
+    lrs = dict(means=1.6e-4, scales=5e-3, quats=1e-3, opacity=5e-2, sh=2.5e-3)
+    acc_g = torch.zeros(N, dtype=torch.float32, device=dev)
+    acc_c = torch.zeros(N, dtype=torch.int32, device=dev)
+    acc_e = torch.zeros(N, dtype=torch.float32, device=dev)
+    acc = B.densify_acc(acc_g, acc_c, acc_e)
+    action = torch.empty(N, dtype=torch.uint8, device=dev)
+    counts = torch.empty(3, dtype=torch.int64, device=dev)
+    dprm = B.densify_params(1.0)
+
+    def run(t):
+        B.ls_loss(rast.cams, rast.image, target, dimg, lossv, lws)
+        for k in params:
+            B.ls_adam(B.adam_params(lrs[k], t), params[k], grads[k], *state[k])
+        B.ls_densify_stats(rast.cfg, rast.cams, rast.ws, rast.capacity, acc)
+        B.ls_densify_select(dprm, N, params["scales"], params["opacity"], acc, action, counts)
+
+    for t in range(1, warmup + 1):
+        run(t)
+    torch.cuda.synchronize()
+    B.ls_profile_read(reset=True)
+    B.ls_profile_enable(True)
+    for t in range(warmup + 1, warmup + steps + 1):
+        run(t)
+    torch.cuda.synchronize()
+    B.ls_profile_enable(False)
+    kt = {n: (c, t) for n, c, t in B.ls_profile_read(reset=True)}
+    n_params = sum(int(v.numel()) for v in sp.values())
+    cost = {"loss": 12.0 * 3 * P, "adam": 28.0 * n_params,
+            "densify_stats": 44.0 * M + 24.0 * N, "densify_select": 29.0 * N}
+    out = {}
+    for name, amount in cost.items():
+        if name not in kt:
+            continue
+        ms = kt[name][1] / steps
+        gbs = amount / (ms * 1e-3) / 1e9
+        out[name] = dict(ms=round(ms, 4), algorithmic_bytes=amount, achieved_gbs=round(gbs, 1),
+                         frac=round(gbs / HBM_PEAK_GBS, 4))
+    out["loss_per_view"] = [round(float(x), 6) for x in lossv.cpu().tolist()]
+    out["densify_counts"] = counts.cpu().tolist()
+    out["note"] = ("per call over the 8-view step; Adam over all %d parameters in 5 groups; "
+                   "algorithmic bytes as in bench.training_stages" % n_params)
+    del lws, dimg, state, params
+    return out
+
 
 def main():
     args = parse()
@@ -357,6 +427,14 @@ def main():
                           "kernel only); linear lambda 2.5, Gaussian lambda 1 with the 3-sigma cut")
         log(f"bench: family {family}")
 
+    train = None
+    if not args.no_train_stages:
+        log("bench: training-step stages (loss, Adam, densification)")
+        step_batched()
+        torch.cuda.synchronize()
+        train = training_stages(B, S, torch, rast, sp, grads, cams, args.steps, args.warmup)
+        log(f"bench: training stages {train}")
+
     # ---- roofline of the dominant kernel --------------------------------------
     w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q, Qc=Qc)
     kernels = []
@@ -421,6 +499,7 @@ def main():
                   "note": "same step launched eagerly with an event pair around every kernel"},
         "per_view": per_view,
         "kernel_family": family,
+        "training_stages": train,
         "roofline": roof,
         "kernels": kernels[:12],
         "cpu_baseline": cpu,

@@ -3,11 +3,10 @@
 // and dL/dimage.  SSIM (Wang et al. 2004) with an 11 x 11 Gaussian window of
 // sigma 1.5 (normalised), zero padding, C1 = 0.01^2, C2 = 0.03^2.
 //
-// Two passes, each over 32 x 16 pixel tiles of one channel (up to 16 cameras
-// per launch, one block per tile and channel) with a
-// 5-pixel halo staged in LDS and the window applied separably (a row pass
-// into LDS, then a column pass), all in FP64 (full rate on CDNA; the local
-// variances sxx - mx^2 cancel badly in FP32):
+// Two passes, each over 48 x 16 pixel tiles of one channel (up to 16 cameras
+// per launch, one block per tile and channel), the window applied separably
+// (a column pass in registers into LDS, then a row pass), all in FP64 (the
+// local variances sxx - mx^2 cancel badly in FP32):
 //   1. local moments mx, my, sxx, syy, sxy; the SSIM map S and its partial
 //      derivatives dS/dmx, dS/dsxx, dS/dsxy (written per pixel, FP64), and
 //      the block's sums of S, |x - y|, (x - y)^2 (one FP64 atomic each);
@@ -17,6 +16,7 @@
 // A last kernel turns the sums into the per-camera loss.  The derivative maps
 // (72 bytes per pixel) and the sums (24 bytes per camera) live in the
 // caller's workspace.
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -27,20 +27,21 @@ namespace lsplat {
 
 namespace {
 
-constexpr int kLTX = 32, kLTY = 16, kHalo = 5, kWin = 11;
-constexpr int kLX = kLTX + 2 * kHalo, kLY = kLTY + 2 * kHalo;   // 42 x 26 staged
+// Tiles of 48 x 16 outputs.  The column pass runs first, straight from
+// global memory: each of 58 x 4 threads owns one column of the tile plus its
+// 5-pixel halo and 4 consecutive output rows, sliding the 11-row window over
+// 14 loaded rows in registers, and leaves its column sums in LDS.  The row
+// pass then gives each thread 3 consecutive outputs of one row from 13 LDS
+// values per sum.  Both passes together read about 220 LDS bytes per output.
+constexpr int kLTX = 48, kLTY = 16, kHalo = 5, kWin = 11;
+constexpr int kLX = kLTX + 2 * kHalo;            // 58 staged columns
+constexpr int kSeg = 4;                           // output rows per column thread
+constexpr int kColThreads = kLX * (kLTY / kSeg);  // 232
+constexpr int kRowOut = 3;                        // outputs per row thread
+constexpr int kLXP = kLX + 1;                     // padded LDS row
+static_assert((kLTX / kRowOut) * kLTY == 256, "row pass covers the tile with 256 threads");
 constexpr double kC1 = 0.0001, kC2 = 0.0009;
 constexpr double kWL1 = 0.6, kWL2 = 0.2, kWSSIM = 0.2;
-
-// the normalised 1D window, built by the first kWin threads
-__device__ __forceinline__ void window_1d(double* g) {
-  const int t = threadIdx.x;
-  if (t < kWin) {
-    double s = 0.0;
-    for (int k = 0; k < kWin; ++k) s += exp(-(double)((k - kHalo) * (k - kHalo)) / 4.5);
-    g[t] = exp(-(double)((t - kHalo) * (t - kHalo)) / 4.5) / s;
-  }
-}
 
 __device__ __forceinline__ double wave_sum_d(double v) {
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -51,6 +52,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // counts (at most kLossCams entries, uniform across the block).
 constexpr int kLossCams = 16;
 struct LossArgs {
+  double g[kWin];                 // the normalised 1D window (host-computed)
   int32_t count;                  // cameras in this launch
   int32_t cam0;                   // global index of the first one
   int32_t W[kLossCams], H[kLossCams], GX[kLossCams];
@@ -79,71 +81,100 @@ __device__ __forceinline__ LossTile loss_tile(const LossArgs& a) {
   return t;
 }
 
-// pass 1: one (camera, 32 x 16 tile, channel) per block of 256 threads
+// pass 1: one (camera, 48 x 16 tile, channel) per block of 256 threads
 __global__ __launch_bounds__(256) void ssim_moments_kernel(
     LossArgs a, const float* __restrict__ img, const float* __restrict__ tgt,
     double* __restrict__ coef, double* __restrict__ acc) {
-  __shared__ double sx[kLY][kLX + 1], sy[kLY][kLX + 1];
-  __shared__ double hm[5][kLY][kLTX];
-  __shared__ double g[kWin];
+  __shared__ double vm[5][kLTY][kLXP];
   __shared__ double red[3][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const LossTile t = loss_tile(a);
   const int W = t.W, H = t.H, x0 = t.x0, y0 = t.y0;
   const float* xi = img + t.base;
   const float* yi = tgt + t.base;
-  // the derivative maps follow the image layout, three maps per channel
-  double* cm = coef + 3 * t.base;
-  window_1d(g);
-  for (int i = tid; i < kLY * kLX; i += 256) {
-    const int r = i / kLX, c = i % kLX;
-    const int gy = y0 - kHalo + r, gx = x0 - kHalo + c;
-    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-    const int64_t o = (int64_t)gy * W + gx;
-    sx[r][c] = in ? (double)xi[o] : 0.0;
-    sy[r][c] = in ? (double)yi[o] : 0.0;
-  }
-  __syncthreads();
-  for (int i = tid; i < kLY * kLTX; i += 256) {
-    const int r = i / kLTX, c = i % kLTX;
-    double mx = 0, my = 0, xx = 0, yy = 0, xy = 0;
+  // this thread's row-pass outputs; their own pixel values are fetched first
+  // (clamped into the image) so that the load overlaps the column pass
+  const int row = tid / (kLTX / kRowOut), c0 = (tid % (kLTX / kRowOut)) * kRowOut;
+  const int py = y0 + row;
+  float cx[kRowOut], cy[kRowOut];
 #pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const double u = sx[r][c + k], v = sy[r][c + k], w = g[k];
-      mx = fma(w, u, mx);
-      my = fma(w, v, my);
-      xx = fma(w, u * u, xx);
-      yy = fma(w, v * v, yy);
-      xy = fma(w, u * v, xy);
+  for (int q = 0; q < kRowOut; ++q) {
+    const int64_t o = (int64_t)min(py, H - 1) * W + min(x0 + c0 + q, W - 1);
+    cx[q] = xi[o];
+    cy[q] = yi[o];
+  }
+  if (tid < kColThreads) {
+    const int col = tid % kLX, seg = tid / kLX;
+    const int gx = x0 - kHalo + col;
+    const int r0 = seg * kSeg;                    // first output row (tile-relative)
+    // every load is issued (clamped into the image) and its bits masked
+    // afterwards, so the 28 loads go out back to back without a branch
+    // between them
+    const bool xin = gx >= 0 && gx < W;
+    const int gxc = min(max(gx, 0), W - 1);
+    double u[kSeg + kWin - 1], v[kSeg + kWin - 1];
+#pragma unroll
+    for (int j = 0; j < kSeg + kWin - 1; ++j) {
+      const int gy = y0 - kHalo + r0 + j;
+      const int64_t o = (int64_t)min(max(gy, 0), H - 1) * W + gxc;
+      const int keep = (xin && gy >= 0 && gy < H) ? -1 : 0;
+      u[j] = (double)__int_as_float(__float_as_int(xi[o]) & keep);
+      v[j] = (double)__int_as_float(__float_as_int(yi[o]) & keep);
     }
-    hm[0][r][c] = mx; hm[1][r][c] = my; hm[2][r][c] = xx; hm[3][r][c] = yy; hm[4][r][c] = xy;
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+      double mx = 0, my = 0, xx = 0, yy = 0, xy = 0;
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) {
+        const double w = a.g[k], p = u[j + k], q = v[j + k];
+        mx = fma(w, p, mx);
+        my = fma(w, q, my);
+        xx = fma(w, p * p, xx);
+        yy = fma(w, q * q, yy);
+        xy = fma(w, p * q, xy);
+      }
+      vm[0][r0 + j][col] = mx; vm[1][r0 + j][col] = my; vm[2][r0 + j][col] = xx;
+      vm[3][r0 + j][col] = yy; vm[4][r0 + j][col] = xy;
+    }
   }
   __syncthreads();
   double ss = 0.0, s1 = 0.0, s2 = 0.0;
-  const int c = tid % kLTX;
-  for (int r = tid / kLTX; r < kLTY; r += 256 / kLTX) {
-    const int px = x0 + c, py = y0 + r;
-    double m[5] = {0, 0, 0, 0, 0};
+  {
+    double m[5][kRowOut];
 #pragma unroll
-    for (int k = 0; k < kWin; ++k)
+    for (int f = 0; f < 5; ++f) {
+      double h[kRowOut + kWin - 1];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) m[f] = fma(g[k], hm[f][r + k][c], m[f]);
-    if (px < W && py < H) {
-      const double mx = m[0], my = m[1];
-      const double a1 = 2.0 * mx * my + kC1;
-      const double a2 = 2.0 * (m[4] - mx * my) + kC2;
-      const double b1 = mx * mx + my * my + kC1;
-      const double b2 = (m[2] - mx * mx) + (m[3] - my * my) + kC2;
-      const double d = b1 * b2;
-      const double S = a1 * a2 / d;
-      const int64_t o = (int64_t)py * W + px;
-      cm[o] = (2.0 * my * (a2 - a1) - 2.0 * mx * S * (b2 - b1)) / d;
-      cm[t.plane + o] = -S / b2;
-      cm[2 * t.plane + o] = 2.0 * a1 / d;
-      const double df = sx[r + kHalo][c + kHalo] - sy[r + kHalo][c + kHalo];
-      ss += S;
-      s1 += fabs(df);
-      s2 += df * df;
+      for (int j = 0; j < kRowOut + kWin - 1; ++j) h[j] = vm[f][row][c0 + j];
+#pragma unroll
+      for (int q = 0; q < kRowOut; ++q) {
+        double acc_f = 0.0;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc_f = fma(a.g[k], h[q + k], acc_f);
+        m[f][q] = acc_f;
+      }
+    }
+    double* cm = coef + 3 * t.base;   // the derivative maps follow the image layout, 3 per channel
+#pragma unroll
+    for (int q = 0; q < kRowOut; ++q) {
+      const int px = x0 + c0 + q;
+      if (px < W && py < H) {
+        const double mx = m[0][q], my = m[1][q];
+        const double a1 = 2.0 * mx * my + kC1;
+        const double a2 = 2.0 * (m[4][q] - mx * my) + kC2;
+        const double b1 = mx * mx + my * my + kC1;
+        const double b2 = (m[2][q] - mx * mx) + (m[3][q] - my * my) + kC2;
+        const double d = b1 * b2;
+        const double S = a1 * a2 / d;
+        const int64_t o = (int64_t)py * W + px;
+        cm[o] = (2.0 * my * (a2 - a1) - 2.0 * mx * S * (b2 - b1)) / d;
+        cm[t.plane + o] = -S / b2;
+        cm[2 * t.plane + o] = 2.0 * a1 / d;
+        const double df = (double)cx[q] - (double)cy[q];
+        ss += S;
+        s1 += fabs(df);
+        s2 += df * df;
+      }
     }
   }
   ss = wave_sum_d(ss);
@@ -158,58 +189,82 @@ __global__ __launch_bounds__(256) void ssim_moments_kernel(
   if (tid < 3) {
     // sums enter already divided by the camera's 3 H W values
     const double inv_n = 1.0 / (3.0 * (double)t.plane);
-    const double v = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
-    atomicAdd(acc + 3 * (a.cam0 + t.k) + tid, v * inv_n);
+    const double val = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+    atomicAdd(acc + 3 * (a.cam0 + t.k) + tid, val * inv_n);
   }
 }
 
-// pass 2: the window over the derivative maps, then the gradient
+// pass 2: the window over the three derivative maps (same two-pass
+// structure), then the gradient of the weighted loss
 __global__ __launch_bounds__(256) void ssim_grad_kernel(
     LossArgs a, const float* __restrict__ img, const float* __restrict__ tgt,
     const double* __restrict__ coef, float* __restrict__ grad) {
-  __shared__ double sc[3][kLY][kLX + 1];
-  __shared__ double hb[3][kLY][kLTX];
-  __shared__ double g[kWin];
+  __shared__ double vb[3][kLTY][kLXP];
   const int tid = threadIdx.x;
   const LossTile t = loss_tile(a);
   const int W = t.W, H = t.H, x0 = t.x0, y0 = t.y0;
   const double* cm = coef + 3 * t.base;
+  const int row = tid / (kLTX / kRowOut), c0 = (tid % (kLTX / kRowOut)) * kRowOut;
+  const int py = y0 + row;
+  float cx[kRowOut], cy[kRowOut];
+#pragma unroll
+  for (int q = 0; q < kRowOut; ++q) {
+    const int64_t o = t.base + (int64_t)min(py, H - 1) * W + min(x0 + c0 + q, W - 1);
+    cx[q] = img[o];
+    cy[q] = tgt[o];
+  }
+  if (tid < kColThreads) {
+    const int col = tid % kLX, seg = tid / kLX;
+    const int gx = x0 - kHalo + col;
+    const int r0 = seg * kSeg;
+    const bool xin = gx >= 0 && gx < W;
+    const int gxc = min(max(gx, 0), W - 1);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      double u[kSeg + kWin - 1];
+#pragma unroll
+      for (int j = 0; j < kSeg + kWin - 1; ++j) {
+        const int gy = y0 - kHalo + r0 + j;
+        const double val = cm[f * t.plane + (int64_t)min(max(gy, 0), H - 1) * W + gxc];
+        // zero outside the image by masking the bits: the value is always
+        // used, so the load cannot be moved into a branch of its own
+        const long long keep = (xin && gy >= 0 && gy < H) ? -1ll : 0ll;
+        u[j] = __longlong_as_double(__double_as_longlong(val) & keep);
+      }
+#pragma unroll
+      for (int j = 0; j < kSeg; ++j) {
+        double acc_f = 0.0;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc_f = fma(a.g[k], u[j + k], acc_f);
+        vb[f][r0 + j][col] = acc_f;
+      }
+    }
+  }
+  __syncthreads();
+  double bl[3][kRowOut];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    double h[kRowOut + kWin - 1];
+#pragma unroll
+    for (int j = 0; j < kRowOut + kWin - 1; ++j) h[j] = vb[f][row][c0 + j];
+#pragma unroll
+    for (int q = 0; q < kRowOut; ++q) {
+      double acc_f = 0.0;
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) acc_f = fma(a.g[k], h[q + k], acc_f);
+      bl[f][q] = acc_f;
+    }
+  }
   const double inv_n = 1.0 / (3.0 * (double)t.plane);
-  window_1d(g);
-  for (int i = tid; i < kLY * kLX; i += 256) {
-    const int r = i / kLX, c = i % kLX;
-    const int gy = y0 - kHalo + r, gx = x0 - kHalo + c;
-    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-    const int64_t o = (int64_t)gy * W + gx;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) sc[f][r][c] = in ? cm[f * t.plane + o] : 0.0;
-  }
-  __syncthreads();
-  for (int i = tid; i < kLY * kLTX; i += 256) {
-    const int r = i / kLTX, c = i % kLTX;
-    double v[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < kWin; ++k)
-#pragma unroll
-      for (int f = 0; f < 3; ++f) v[f] = fma(g[k], sc[f][r][c + k], v[f]);
-#pragma unroll
-    for (int f = 0; f < 3; ++f) hb[f][r][c] = v[f];
-  }
-  __syncthreads();
-  const int c = tid % kLTX;
-  for (int r = tid / kLTX; r < kLTY; r += 256 / kLTX) {
-    const int px = x0 + c, py = y0 + r;
+  for (int q = 0; q < kRowOut; ++q) {
+    const int px = x0 + c0 + q;
     if (px >= W || py >= H) continue;
-    double v[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < kWin; ++k)
-#pragma unroll
-      for (int f = 0; f < 3; ++f) v[f] = fma(g[k], hb[f][r + k][c], v[f]);
     const int64_t o = t.base + (int64_t)py * W + px;
-    const double x = (double)img[o], y = (double)tgt[o];
+    const double x = (double)cx[q], y = (double)cy[q];
     const double df = x - y;
     const double sg = df > 0.0 ? 1.0 : (df < 0.0 ? -1.0 : 0.0);
-    const double dssim = v[0] + 2.0 * x * v[1] + y * v[2];
+    const double dssim = bl[0][q] + 2.0 * x * bl[1][q] + y * bl[2][q];
     grad[o] = (float)((kWL1 * sg + kWL2 * 2.0 * df - kWSSIM * dssim) * inv_n);
   }
 }
@@ -245,10 +300,16 @@ hipError_t launch_loss(const int32_t* W, const int32_t* H, int C, const float* i
   ProfScope ps("loss", s);
   hipLaunchKernelGGL(loss_zero_kernel, dim3((3 * C + 255) / 256), dim3(256), 0, s, acc, 3 * C);
   if ((e = hipGetLastError())) return e;
+  double win[kWin], wsum = 0.0;
+  for (int k = 0; k < kWin; ++k) {
+    win[k] = exp(-(double)((k - kHalo) * (k - kHalo)) / 4.5);   // sigma 1.5
+    wsum += win[k];
+  }
   int64_t pix = 0;
   for (int first = 0; first < C; first += kLossCams) {
     LossArgs a;
     memset(&a, 0, sizeof(a));
+    for (int k = 0; k < kWin; ++k) a.g[k] = win[k] / wsum;
     a.cam0 = first;
     a.count = std::min(kLossCams, C - first);
     a.blk[0] = 0;

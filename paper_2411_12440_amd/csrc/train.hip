@@ -114,38 +114,52 @@ __global__ void counts_zero_kernel(unsigned long long* __restrict__ c) {
 }
 
 // The decision compares in FP64 on the stored FP32 statistics; action bits
-// 1 duplicate, 2 split, 4 prune.  Per-wave ballots feed the three counters.
+// 1 duplicate, 2 split, 4 prune.  Each thread counts its own decisions over
+// the grid-stride loop; the block sums them in LDS and adds once per counter.
 __global__ __launch_bounds__(kTrainThreads) void densify_select_kernel(
     int64_t N, SelectArgs a, const float* __restrict__ scales, const float* __restrict__ opac,
     const float* __restrict__ acc_grad, const int32_t* __restrict__ acc_count,
     const float* __restrict__ acc_ext, uint8_t* __restrict__ action,
     unsigned long long* __restrict__ counts) {
+  __shared__ unsigned int red[3][kTrainThreads / 64];
   const int64_t stride = (int64_t)gridDim.x * kTrainThreads;
-  const int lane = threadIdx.x & 63;
-  for (int64_t base = (int64_t)blockIdx.x * kTrainThreads; base < N; base += stride) {
-    const int64_t i = base + threadIdx.x;
+  unsigned int n_dup = 0, n_split = 0, n_prune = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kTrainThreads + threadIdx.x; i < N; i += stride) {
     int act = 0;
-    if (i < N) {
-      const int32_t cnt = acc_count[i];
-      const bool high = cnt > 0 && (double)acc_grad[i] / (double)cnt > a.grad;
-      const double s = (double)fmaxf(fmaxf(scales[i], scales[N + i]), scales[2 * N + i]);
-      const bool small = s <= a.s3g * a.scene_scale;
-      const double e = (double)acc_ext[i];
-      const bool split = (high && !small) || (a.grow2d && e > a.s2g);
-      if (split)
-        act |= 2;
-      else if (high && small)
-        act |= 1;
-      if ((double)opac[i] < a.op || (a.prune_big && (s > a.s3p * a.scene_scale || e > a.s2p)))
-        act |= 4;
-      action[i] = (uint8_t)act;
-    }
-    if (counts) {
-      for (int b = 0; b < 3; ++b) {
-        const unsigned long long bal = __ballot((act >> b) & 1);
-        if (lane == 0 && bal) atomicAdd(counts + b, (unsigned long long)__popcll(bal));
-      }
-    }
+    const int32_t cnt = acc_count[i];
+    const bool high = cnt > 0 && (double)acc_grad[i] / (double)cnt > a.grad;
+    const double s = (double)fmaxf(fmaxf(scales[i], scales[N + i]), scales[2 * N + i]);
+    const bool small = s <= a.s3g * a.scene_scale;
+    const double e = (double)acc_ext[i];
+    const bool split = (high && !small) || (a.grow2d && e > a.s2g);
+    if (split)
+      act |= 2;
+    else if (high && small)
+      act |= 1;
+    if ((double)opac[i] < a.op || (a.prune_big && (s > a.s3p * a.scene_scale || e > a.s2p)))
+      act |= 4;
+    action[i] = (uint8_t)act;
+    n_dup += act & 1;
+    n_split += (act >> 1) & 1;
+    n_prune += (act >> 2) & 1;
+  }
+  if (!counts) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int d = 32; d > 0; d >>= 1) {
+    n_dup += __shfl_xor(n_dup, d, 64);
+    n_split += __shfl_xor(n_split, d, 64);
+    n_prune += __shfl_xor(n_prune, d, 64);
+  }
+  if (lane == 0) {
+    red[0][wave] = n_dup;
+    red[1][wave] = n_split;
+    red[2][wave] = n_prune;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long v = 0;
+    for (int w = 0; w < kTrainThreads / 64; ++w) v += red[threadIdx.x][w];
+    if (v) atomicAdd(counts + threadIdx.x, v);
   }
 }
 
@@ -205,7 +219,8 @@ hipError_t launch_densify_select(const ls_densify_params* prm, int64_t n, const 
     a.scene_scale = prm->scene_scale;
     a.grow2d = prm->grow2d;
     a.prune_big = prm->prune_big;
-    hipLaunchKernelGGL(densify_select_kernel, dim3(grid_for(n)), dim3(kTrainThreads), 0, s, n, a,
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + kTrainThreads - 1) / kTrainThreads, 2048);
+    hipLaunchKernelGGL(densify_select_kernel, dim3(blocks), dim3(kTrainThreads), 0, s, n, a,
                        scales, opacity, acc->grad, acc->count, acc->max_extent, action,
                        (unsigned long long*)counts);
   }
