@@ -214,6 +214,53 @@ def image_pair(widths, heights, seed: int, noise: float | None = 0.1):
     return (np.concatenate(imgs).astype(np.float32), np.concatenate(tgts).astype(np.float32))
 
 
+PATTERNS = ("stripes", "checker", "circles")
+
+
+def pattern(kind: str, freq: int, width: int, height: int, seed: int) -> np.ndarray:
+    """A two-colour test pattern [3, H, W] float32 with hard edges: vertical
+    stripes with ``freq`` cycles across the width, a checkerboard of squares
+    W / (2 freq) pixels wide, or concentric rings with ``freq`` cycles from
+    the centre to the half-width.  Pixel (x, y) is sampled at its centre;
+    the two colours are U[0, 1]^3 from ``seed``."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    c0, c1 = g.uniform(0.0, 1.0, 3), g.uniform(0.0, 1.0, 3)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64) + 0.5
+    band = 2.0 * freq / width
+    if kind == "stripes":
+        sel = np.floor(band * xx).astype(np.int64) % 2
+    elif kind == "checker":
+        sel = (np.floor(band * xx).astype(np.int64) + np.floor(band * yy).astype(np.int64)) % 2
+    elif kind == "circles":
+        r = np.hypot(xx - width / 2.0, yy - height / 2.0)
+        sel = np.floor(2.0 * band * r).astype(np.int64) % 2
+    else:
+        raise ValueError(f"unknown pattern {kind!r}")
+    img = np.where(sel[None] == 0, c0[:, None, None], c1[:, None, None])
+    return img.astype(np.float32)
+
+
+def plane_splats(n: int, width: int, height: int, seed: int, distance: float = 3.0) -> Scene:
+    """``n`` flat splats on the plane z = 0 seen by ``front_camera(width,
+    height, distance)``: centres uniform over the visible rectangle, equal
+    in-plane scales sqrt(area / n) / 2 (z scale 1% of that), a rotation about
+    z uniform in [0, pi), opacity 0.5, colour U[0, 1]^3 (SH degree 0)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    hw = distance * math.tan(math.radians(30.0))
+    hh = hw * height / width
+    means = np.zeros((n, 3))
+    means[:, 0] = g.uniform(-hw, hw, n)
+    means[:, 1] = g.uniform(-hh, hh, n)
+    s0 = 0.5 * math.sqrt(4.0 * hw * hh / n)
+    scales = np.tile([s0, s0, 0.01 * s0], (n, 1))
+    th = g.uniform(0.0, math.pi, n)
+    quats = np.stack([np.cos(th / 2), np.zeros(n), np.zeros(n), np.sin(th / 2)], axis=1)
+    colour = g.uniform(0.0, 1.0, (n, 3))
+    sh = ((colour - 0.5) / _SH_DC)[:, None, :]
+    return Scene(means.astype(np.float32), scales.astype(np.float32), quats.astype(np.float32),
+                 np.full(n, 0.5, np.float32), sh.astype(np.float32), 0)
+
+
 # ---------------------------------------------------------------------------
 # The five workloads.  Seeds: scene k -> 1000 + k, extra scene s -> 5000 + s,
 # upstream gradient -> 7000 + k, resolution permutation -> 9000 + k.
