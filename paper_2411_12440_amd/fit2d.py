@@ -33,8 +33,10 @@ from .rasterizer import Rasterizer
 
 # kernel -> DA factor of the appendix (the Gaussian's is 1); "linear_ags" is
 # the linear kernel with adaptive gradient scaling (the paper's full method)
-LAMBDA = dict(linear=2.5, linear_ags=2.5, gaussian=1.0, laplacian=1.0, cosine=2.5,
-              quadratic=6.0)
+# under the D'^2 reading of its weight, "linear_ags_n" under the D'^2 / lambda^2
+# reading
+LAMBDA = dict(linear=2.5, linear_ags=2.5, linear_ags_n=2.5, gaussian=1.0, laplacian=1.0,
+              cosine=2.5, quadratic=6.0)
 # 3DGS learning rates (centres scaled by the half-width of the visible plane)
 LR = dict(means=1.6e-4, scales=5e-3, quats=1e-3, opacity=5e-2, sh=2.5e-3)
 
@@ -49,10 +51,13 @@ class PatternFit:
         self.n = scene0.n
         self.cams = scenes.front_camera(W, H)
         lam = LAMBDA[kernel] if lambda_ is None else lambda_
-        if kernel == "linear_ags":
-            kernel, ags = "linear", True
+        ags_arg = 0
+        if kernel.startswith("linear_ags"):
+            ags, ags_arg = True, 1 if kernel == "linear_ags_n" else 0
+            kernel = "linear"
         self.rast = Rasterizer(self.cams, np.array([0, self.n]), device=self.dev,
-                               kernel=kernel, lambda_=lam, ags=ags, sh_degree=0)
+                               kernel=kernel, lambda_=lam, ags=ags, ags_arg=ags_arg,
+                               sh_degree=0)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(self.dev)
         self.raw = dict(means=t(scene0.means.T), scales=t(np.log(scene0.scales).T),
                         quats=t(scene0.quats.T),
@@ -114,7 +119,8 @@ class PatternFit:
 
 def run_study(size=256, splats=4096, iters=3000, freqs=(4, 16, 32), kernels=None,
               patterns=scenes.PATTERNS, log_every=600, seed=0):
-    kernels = kernels or ["gaussian", "laplacian", "cosine", "quadratic", "linear", "linear_ags"]
+    kernels = kernels or ["gaussian", "laplacian", "cosine", "quadratic", "linear", "linear_ags",
+                          "linear_ags_n"]
     rows = []
     for pi, kind in enumerate(patterns):
         for f in freqs:
