@@ -5,7 +5,9 @@ times (AGS on, 16x16 tiles, seven depth chunks):
     sphere (the benchmark itself);
   * workload 3: 1M splats, 16 cameras of uneven resolution;
   * workload 5: 4 scenes (200k to 2M splats), 64 cameras of mixed
-    resolution, 16 per scene.
+    resolution, 16 per scene;
+  * workload 40 again with the Gaussian kernel (the benchmark's kernel-family
+    leg: lambda 1, 3-sigma cut, no AGS).
 
 The FP64 oracle cannot composite every pixel at these sizes, so each test
 checks
@@ -43,14 +45,14 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _sampled_parity(k, views, tiles_per_view, seed):
+def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5, ags=True):
     import torch
     from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
 
     scene, off, cams = scenes.workload(k)
     N = scene.n
     deg = scene.sh_degree
-    ocfg, gkw = cfg_pair(ags=True, depth_chunks=7)
+    ocfg, gkw = cfg_pair(ags=ags, depth_chunks=7, kernel=kernel, lambda_=lambda_)
     sp = scene_to_device(scene)
     rast = Rasterizer(cams, off, capacity=1 << 24, sh_degree=deg, **gkw)
     rast.forward(sp)
@@ -234,3 +236,11 @@ def test_uneven_cameras_sampled():
 def test_multi_scene_64_cameras_sampled():
     say("case: workload 5 (4 scenes, 3.7M splats, 64 cameras), AGS, depth chunks 7")
     _sampled_parity(5, views=(1, 22, 40, 63), tiles_per_view=2, seed=5)
+
+
+def test_benchmark_gaussian_kernel_sampled():
+    """The benchmark's kernel-family leg: the same scene and views with the
+    Gaussian kernel (lambda 1, 3-sigma cut, no AGS)."""
+    say("case: workload 40 with the Gaussian kernel, no AGS, depth chunks 7")
+    _sampled_parity(40, views=(3,), tiles_per_view=5, seed=41, kernel="gaussian", lambda_=1.0,
+                    ags=False)
