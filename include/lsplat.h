@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 150
+#define LSPLAT_VERSION 160
 
 typedef enum {
   LS_OK = 0,
@@ -105,6 +105,14 @@ typedef enum {
  *            tile's list is the prefix of its complete list that the
  *            composite can reach.  Images and gradients are identical to the
  *            complete-list mode.
+ * deterministic  0: the backward pass sums each splat's per-tile gradients
+ *            with FP64 atomics (order-dependent in the last bits).  1: it
+ *            stores every list entry's per-tile sums in the workspace, orders
+ *            the entries by pair (a stable radix sort) and sums each pair's
+ *            entries in list order, so that gradients are bitwise
+ *            reproducible from run to run and between the batched and the
+ *            per-view calls.  Costs 88 bytes of workspace per intersection of
+ *            capacity and a slower backward pass.
  */
 typedef struct ls_config {
   float lambda;
@@ -118,6 +126,7 @@ typedef struct ls_config {
   int32_t batch;
   int32_t depth_chunks;
   int32_t kernel;
+  int32_t deterministic;
 } ls_config;
 
 enum {

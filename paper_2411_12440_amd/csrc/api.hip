@@ -49,6 +49,8 @@ static ls_status check_config(const ls_config* c) {
   if (c->sh_degree < 0 || c->sh_degree > 3) return fail(LS_ERR_INVALID_ARG, "sh_degree must be 0..3");
   if (c->kernel < LS_KERNEL_LINEAR || c->kernel > LS_KERNEL_QUADRATIC)
     return fail(LS_ERR_INVALID_ARG, "kernel must be 0..4 (LS_KERNEL_*)");
+  if (c->deterministic != 0 && c->deterministic != 1)
+    return fail(LS_ERR_INVALID_ARG, "deterministic must be 0 or 1");
   if (c->ags && c->kernel != LS_KERNEL_LINEAR)
     return fail(LS_ERR_INVALID_ARG, "ags is defined for the linear kernel only");
   if (!tile_shape_ok(c->tile_w, c->tile_h))
@@ -174,6 +176,13 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   if (p->K > 1) {
     p->state = take(32 * (size_t)p->P);
     p->done = take((size_t)p->P);
+  }
+  if (cfg->deterministic) {
+    p->det_partial = take(8 * (size_t)kGrad2d * CAP);
+    p->det_k0 = take(4 * CAP);
+    p->det_v0 = take(4 * CAP);
+    p->det_k1 = take(4 * CAP);
+    p->det_v1 = take(4 * CAP);
   }
   L.total_bytes = off;
   return LS_OK;

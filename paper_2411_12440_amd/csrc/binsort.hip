@@ -968,6 +968,33 @@ hipError_t tile_sort_and_ranges(const Plan& p, char* ws, const int64_t* base_dev
   return hipGetLastError();
 }
 
+// Deterministic backward: every list entry's per-tile gradient sums sit in
+// partial[f][e] (e its position in the chunk-concatenated lists).  A stable
+// LSD radix sort of the entries by pair id (identity values first, so equal
+// pairs keep ascending positions) groups each pair's entries in list order,
+// and one thread per pair adds them in that order.
+__global__ __launch_bounds__(256) void det_reduce_kernel(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ pos,
+    const int64_t* __restrict__ n_dev, const double* __restrict__ partial, int64_t cap,
+    double* __restrict__ grad2d, int64_t M) {
+  const int64_t n = *n_dev;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const uint32_t m = keys[i];
+    if (i > 0 && keys[i - 1] == m) continue;
+    double acc[kGrad2d];
+#pragma unroll
+    for (int f = 0; f < kGrad2d; ++f) acc[f] = 0.0;
+    for (int64_t j = i; j < n && keys[j] == m; ++j) {
+      const int64_t e = pos[j];
+#pragma unroll
+      for (int f = 0; f < kGrad2d; ++f) acc[f] += partial[(int64_t)f * cap + e];
+    }
+#pragma unroll
+    for (int f = 0; f < kGrad2d; ++f) grad2d[(int64_t)f * M + m] = acc[f];
+  }
+}
+
 // The buffer the key generation writes to, so that the sort ends in (keys, vals).
 void keygen_targets(const Plan& p, char* ws, uint32_t** k0, uint32_t** v0) {
   const int passes = (p.tile_bits + 7) / 8;
@@ -976,6 +1003,37 @@ void keygen_targets(const Plan& p, char* ws, uint32_t** k0, uint32_t** v0) {
 }
 
 }  // namespace
+
+static const char* const kDetNames[3] = {"detsort_upsweep", "detsort_scan", "detsort_downsweep"};
+
+hipError_t launch_det_reduce(const Plan& p, char* ws, hipStream_t s) {
+  hipError_t e;
+  const int64_t* n_dev = (const int64_t*)(ws + p.lay.chunk_base) + p.K;
+  int bits = 0;
+  while (bits < 32 && ((p.M - 1) >> bits) > 0) ++bits;
+  const int passes = std::max(1, (bits + 7) / 8);
+  const uint32_t* vals = (const uint32_t*)(ws + p.lay.vals);
+  uint32_t* kb[2] = {(uint32_t*)(ws + p.det_k0), (uint32_t*)(ws + p.det_k1)};
+  uint32_t* vb[2] = {(uint32_t*)(ws + p.det_v0), (uint32_t*)(ws + p.det_v1)};
+  uint32_t* hist = (uint32_t*)(ws + p.hist);
+  uint32_t* tot = (uint32_t*)(ws + p.digit_tot);
+  if ((e = radix_pass<true, true>(kDetNames, vals, nullptr, kb[0], vb[0], nullptr, n_dev, 0, 0,
+                                  p.sort_blocks, hist, tot, s)))
+    return e;
+  int cur = 0;
+  for (int pass = 1; pass < passes; ++pass) {
+    if ((e = radix_pass<false, true>(kDetNames, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], nullptr,
+                                     n_dev, 0, 8 * pass, p.sort_blocks, hist, tot, s)))
+      return e;
+    cur ^= 1;
+  }
+  const unsigned blocks = (unsigned)std::min<int64_t>((p.cap + 255) / 256, 4096);
+  ProfScope ps("det_reduce", s);
+  hipLaunchKernelGGL(det_reduce_kernel, dim3(std::max(1u, blocks)), dim3(256), 0, s, kb[cur],
+                     vb[cur], n_dev, (const double*)(ws + p.det_partial), p.cap,
+                     (double*)(ws + p.lay.grad2d), p.M);
+  return hipGetLastError();
+}
 
 hipError_t launch_bin_sort(const Plan& p, const ls_config* cfg, char* ws, hipStream_t s) {
   (void)cfg;

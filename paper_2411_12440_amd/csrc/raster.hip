@@ -454,10 +454,14 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
     RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
-    double* __restrict__ grad2d) {
+    double* __restrict__ grad2d, double* __restrict__ partial, int64_t cap) {
   constexpr int PPL = raster_ppl<TW, TH>();
   constexpr int NTB = raster_threads<TW, TH>();
   constexpr int NWB = NTB / 64;
+  // With at most two waves per tile, the LDS sums of a staged entry (two adds
+  // onto zero) do not depend on the order of the waves' atomics, so a tile's
+  // per-entry sums are reproducible; the deterministic mode relies on it.
+  static_assert(NWB <= 2, "per-tile sums are order-independent for at most two waves");
   // at most 128 entries per batch, so that the FP64 accumulators fit beside
   // the staged entries without lowering the occupancy
   constexpr int NS = NTB < 128 ? NTB : 128;
@@ -657,14 +661,34 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     }
     __syncthreads();
     if (tid < cnt) {
-      const int64_t m = (int64_t)st.m[tid];
+      if (partial) {
+        // deterministic mode: the entry's own slot (its position in the
+        // chunk-concatenated lists); the pair sums are formed afterwards
+        const int32_t q = st.pos[tid];
+        int cc = 0;
+        while (cc + 1 < K && s_segpre[cc + 1] <= q) ++cc;
+        const int64_t e = s_segbase[cc] + (q - s_segpre[cc]);
 #pragma unroll
-      for (int f = 0; f < kGrad2d; ++f) {
-        const double v = s_acc[tid][f];
-        if (v != 0.0) unsafeAtomicAdd(grad2d + (int64_t)f * M + m, v);
+        for (int f = 0; f < kGrad2d; ++f) partial[(int64_t)f * cap + e] = s_acc[tid][f];
+      } else {
+        const int64_t m = (int64_t)st.m[tid];
+#pragma unroll
+        for (int f = 0; f < kGrad2d; ++f) {
+          const double v = s_acc[tid][f];
+          if (v != 0.0) unsafeAtomicAdd(grad2d + (int64_t)f * M + m, v);
+        }
       }
     }
   }
+}
+
+// zero rows [0, n) of the deterministic mode's per-entry sums (row f at f * cap)
+__global__ void det_zero_kernel(double* __restrict__ partial, int64_t cap,
+                                const int64_t* __restrict__ n_dev) {
+  const int64_t n = *n_dev;
+  double* row = partial + (int64_t)blockIdx.y * cap;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    row[i] = 0.0;
 }
 
 __global__ void zero_kernel(float* __restrict__ p, int64_t n) {
@@ -771,12 +795,22 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     RasterParams rp = make_params(cfg);
     const int npix = cfg->tile_w * cfg->tile_h;
     const int batch = cfg->batch ? cfg->batch : npix;
+    double* partial = nullptr;
+    if (cfg->deterministic && p.cap > 0) {
+      // entries the backward pass does not stage (culled, or past every
+      // pixel's last contributor) keep zero sums
+      partial = (double*)(ws + p.det_partial);
+      const unsigned blocks = (unsigned)std::min<int64_t>((p.cap + 255) / 256, 4096);
+      ProfScope ps("det_zero", s);
+      hipLaunchKernelGGL(det_zero_kernel, dim3(blocks, kGrad2d), dim3(256), 0, s, partial, p.cap,
+                         chunk_base + p.K);
+    }
     dim3 grid((unsigned)p.T);
     ProfScope ps("raster_bwd", s);
 #define LS_BWD(TW_, TH_, KF_)                                                                      \
   hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_>), grid, dim3(raster_threads<TW_, TH_>()), 0, \
                      s, cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,         \
-                     final_T, last, dL_dimage, dL_dalpha, grad2d)
+                     final_T, last, dL_dimage, dL_dalpha, grad2d, partial, p.cap)
 #define LS_BWD_K(TW_, TH_)                                                                         \
   switch (cfg->kernel) {                                                                           \
     case LS_KERNEL_GAUSSIAN: LS_BWD(TW_, TH_, LS_KERNEL_GAUSSIAN); break;                          \
@@ -793,6 +827,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
 #undef LS_BWD
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (partial && (e = launch_det_reduce(p, ws, s)) != hipSuccess) return e;
   }
   return launch_project_bwd(p, cfg, sp, ws, g, s);
 }

@@ -36,7 +36,7 @@ def cfg_pair(**kw):
                clip=ocfg.clip, bg=ocfg.bg, ags=ocfg.ags, ags_arg=ocfg.ags_arg,
                ags_scope=ocfg.ags_scope, tile_w=ocfg.tile_w, tile_h=ocfg.tile_h,
                batch=kw.get("batch", 0), depth_chunks=kw.get("depth_chunks", 1),
-               kernel=ocfg.kernel)
+               kernel=ocfg.kernel, deterministic=kw.get("deterministic", False))
     return ocfg, gkw
 
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(B.EXPORTS) == set(declared_functions())
-    assert B.ls_version() == 150
+    assert B.ls_version() == 160
 
 
 def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):
@@ -64,7 +64,8 @@ def test_workspace_size_and_layout():
 @pytest.mark.parametrize("field,value", [("lambda_", 0.0), ("eps2d", 0.0), ("alpha_max", 1.0),
                                          ("t_min", -1.0), ("sh_degree", 4), ("ags", 2),
                                          ("batch", 100), ("near_z", -1.0),
-                                         ("depth_chunks", 13), ("kernel", 5), ("kernel", -1)])
+                                         ("depth_chunks", 13), ("kernel", 5), ("kernel", -1),
+                                         ("deterministic", 2)])
 def test_invalid_config_rejected(field, value):
     from paper_2411_12440_amd import binding as B
     cfg = B.make_config()
@@ -116,6 +117,16 @@ def test_null_workspace_and_buffers_rejected():
     st = lib.ls_project(C.byref(cfg), C.byref(sp), C.byref(cams.c), base, len(ws.raw) - 256, 0, None)
     assert st == -1
     assert b"splats.n" in lib.ls_last_error()
+
+
+def test_deterministic_workspace():
+    """The deterministic backward adds 88 bytes per intersection of capacity."""
+    from paper_2411_12440_amd import binding as B
+    cams = _cams(w=(128,), h=(96,), scene=(0,), off=(0, 5000))
+    cap = 1 << 16
+    a = B.ls_workspace_size(B.make_config(), cams, cap)
+    b = B.ls_workspace_size(B.make_config(deterministic=True), cams, cap)
+    assert 88 * cap <= b - a <= 88 * cap + 5 * 256
 
 
 def test_depth_chunks_layout():
