@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--splats", type=int, default=3_200_000)
     ap.add_argument("--ags", type=int, default=1)
     ap.add_argument("--depth-chunks", type=int, default=7)
+    ap.add_argument("--deterministic", type=int, default=0,
+                    help="1: the bitwise-reproducible backward (per-entry sums, pair sort)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-family", action="store_true",
@@ -276,7 +278,8 @@ def main():
     scene, cams = make_workload(args.splats, args.views)
     sp = scene_to_device(scene, dev)
     G_all = torch.from_numpy(S.upstream_grad(cams, 7004)).to(dev)
-    cfgkw = dict(sh_degree=3, ags=bool(args.ags), depth_chunks=args.depth_chunks)
+    cfgkw = dict(sh_degree=3, ags=bool(args.ags), depth_chunks=args.depth_chunks,
+                 deterministic=bool(args.deterministic))
     off = np.array([0, scene.n])
     P = int(sum(int(w) * int(h) for w, h in zip(cams.width, cams.height)))
 
@@ -492,6 +495,7 @@ def main():
                    "entries_built": n_built, "depth_chunks": args.depth_chunks,
                    "chunk_entries": chunk_entries,
                    "pairs_to_last": Q, "contributing_pairs": Qc, "ags": bool(args.ags),
+                   "deterministic": bool(args.deterministic),
                    "tile": "16x16",
                    "parallelism": "single GPU"},
         "eager": {"ms_per_step": round(ms_eager, 4),

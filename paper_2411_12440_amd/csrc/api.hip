@@ -183,6 +183,7 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
     p->det_v0 = take(4 * CAP);
     p->det_k1 = take(4 * CAP);
     p->det_v1 = take(4 * CAP);
+    p->det_cnt = take(8);
   }
   L.total_bytes = off;
   return LS_OK;

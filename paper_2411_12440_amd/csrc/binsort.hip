@@ -968,30 +968,89 @@ hipError_t tile_sort_and_ranges(const Plan& p, char* ws, const int64_t* base_dev
   return hipGetLastError();
 }
 
-// Deterministic backward: every list entry's per-tile gradient sums sit in
-// partial[f][e] (e its position in the chunk-concatenated lists).  A stable
-// LSD radix sort of the entries by pair id (identity values first, so equal
-// pairs keep ascending positions) groups each pair's entries in list order,
-// and one thread per pair adds them in that order.
-__global__ __launch_bounds__(256) void det_reduce_kernel(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ pos,
-    const int64_t* __restrict__ n_dev, const double* __restrict__ partial, int64_t cap,
-    double* __restrict__ grad2d, int64_t M) {
+// Deterministic backward.  A stable LSD radix sort of the list entries by
+// pair id (identity values first, so that a pair's entries keep ascending
+// list positions) gives every entry a slot in pair order; the backward pass
+// stores the entry's nine per-tile sums at partial[9 slot + f], and one
+// thread per pair adds its contiguous slots in order.
+__global__ __launch_bounds__(256) void det_slot_kernel(const uint32_t* __restrict__ pos,
+                                                       const int64_t* __restrict__ n_dev,
+                                                       uint32_t* __restrict__ slot) {
+  const int64_t n = *n_dev;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    slot[pos[i]] = (uint32_t)i;
+}
+
+// Pairs with at most kDetShort entries are summed by one thread in slot
+// order; longer ones are queued and summed by one wave each: lane l adds the
+// segment's slots l, l + 64, ..., then a fixed butterfly combines the lanes.
+// Both rules depend only on the pair's own segment, so a pair's sum is the
+// same wherever its segment lies (batched or per-view calls).
+constexpr int kDetShort = 64;
+
+__global__ void det_count_zero(uint32_t* __restrict__ cnt) {
+  if (threadIdx.x == 0) cnt[0] = 0u;
+}
+
+__global__ __launch_bounds__(256) void det_reduce_short(
+    const uint32_t* __restrict__ keys, const int64_t* __restrict__ n_dev,
+    const double* __restrict__ partial, double* __restrict__ grad2d, int64_t M,
+    uint32_t* __restrict__ long_start, uint32_t* __restrict__ long_cnt) {
   const int64_t n = *n_dev;
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const uint32_t m = keys[i];
     if (i > 0 && keys[i - 1] == m) continue;
+    int64_t j = i + 1;
+    while (j < n && j - i <= kDetShort && keys[j] == m) ++j;
+    if (j - i > kDetShort) {
+      long_start[atomicAdd(long_cnt, 1u)] = (uint32_t)i;
+      continue;
+    }
     double acc[kGrad2d];
 #pragma unroll
     for (int f = 0; f < kGrad2d; ++f) acc[f] = 0.0;
-    for (int64_t j = i; j < n && keys[j] == m; ++j) {
-      const int64_t e = pos[j];
+    for (int64_t k = i; k < j; ++k) {
 #pragma unroll
-      for (int f = 0; f < kGrad2d; ++f) acc[f] += partial[(int64_t)f * cap + e];
+      for (int f = 0; f < kGrad2d; ++f) acc[f] += partial[k * kGrad2d + f];
     }
 #pragma unroll
     for (int f = 0; f < kGrad2d; ++f) grad2d[(int64_t)f * M + m] = acc[f];
+  }
+}
+
+__global__ __launch_bounds__(256) void det_reduce_long(
+    const uint32_t* __restrict__ keys, const int64_t* __restrict__ n_dev,
+    const double* __restrict__ partial, double* __restrict__ grad2d, int64_t M,
+    const uint32_t* __restrict__ long_start, const uint32_t* __restrict__ long_cnt) {
+  const int64_t n = *n_dev;
+  const uint32_t nl = *long_cnt;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * 256) >> 6;
+  for (int64_t w = wave; w < nl; w += waves) {
+    const int64_t i = long_start[w];
+    const uint32_t m = keys[i];
+    double acc[kGrad2d];
+#pragma unroll
+    for (int f = 0; f < kGrad2d; ++f) acc[f] = 0.0;
+    for (int64_t base = i;; base += 64) {
+      const int64_t k = base + lane;
+      const bool mine = k < n && keys[k] == m;
+      if (mine) {
+#pragma unroll
+        for (int f = 0; f < kGrad2d; ++f) acc[f] += partial[k * kGrad2d + f];
+      }
+      // the segment is contiguous: once a lane falls outside it, it ends
+      if (__builtin_amdgcn_ballot_w64(!mine) != 0ull) break;
+    }
+#pragma unroll
+    for (int f = 0; f < kGrad2d; ++f)
+      for (int d = 1; d < 64; d <<= 1) acc[f] += __shfl_xor(acc[f], d, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int f = 0; f < kGrad2d; ++f) grad2d[(int64_t)f * M + m] = acc[f];
+    }
   }
 }
 
@@ -1006,12 +1065,28 @@ void keygen_targets(const Plan& p, char* ws, uint32_t** k0, uint32_t** v0) {
 
 static const char* const kDetNames[3] = {"detsort_upsweep", "detsort_scan", "detsort_downsweep"};
 
-hipError_t launch_det_reduce(const Plan& p, char* ws, hipStream_t s) {
-  hipError_t e;
-  const int64_t* n_dev = (const int64_t*)(ws + p.lay.chunk_base) + p.K;
+// buffers of the pair-order sort: sorted pair ids end in k[cur], the entry
+// positions in v[cur], and the slot of every entry goes to v[cur ^ 1]
+static int det_passes(const Plan& p) {
   int bits = 0;
   while (bits < 32 && ((p.M - 1) >> bits) > 0) ++bits;
-  const int passes = std::max(1, (bits + 7) / 8);
+  return std::max(1, (bits + 7) / 8);
+}
+
+const uint32_t* det_sorted_keys(const Plan& p, char* ws) {
+  const int cur = (det_passes(p) - 1) & 1;
+  return (const uint32_t*)(ws + (cur ? p.det_k1 : p.det_k0));
+}
+
+const uint32_t* det_slots(const Plan& p, char* ws) {
+  const int cur = (det_passes(p) - 1) & 1;
+  return (const uint32_t*)(ws + (cur ? p.det_v0 : p.det_v1));
+}
+
+hipError_t launch_det_order(const Plan& p, char* ws, hipStream_t s) {
+  hipError_t e;
+  const int64_t* n_dev = (const int64_t*)(ws + p.lay.chunk_base) + p.K;
+  const int passes = det_passes(p);
   const uint32_t* vals = (const uint32_t*)(ws + p.lay.vals);
   uint32_t* kb[2] = {(uint32_t*)(ws + p.det_k0), (uint32_t*)(ws + p.det_k1)};
   uint32_t* vb[2] = {(uint32_t*)(ws + p.det_v0), (uint32_t*)(ws + p.det_v1)};
@@ -1027,11 +1102,28 @@ hipError_t launch_det_reduce(const Plan& p, char* ws, hipStream_t s) {
       return e;
     cur ^= 1;
   }
-  const unsigned blocks = (unsigned)std::min<int64_t>((p.cap + 255) / 256, 4096);
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((p.cap + 255) / 256, 4096));
+  ProfScope ps("det_slot", s);
+  hipLaunchKernelGGL(det_slot_kernel, dim3(blocks), dim3(256), 0, s, vb[cur], n_dev, vb[cur ^ 1]);
+  return hipGetLastError();
+}
+
+hipError_t launch_det_reduce(const Plan& p, char* ws, hipStream_t s) {
+  const int64_t* n_dev = (const int64_t*)(ws + p.lay.chunk_base) + p.K;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((p.cap + 255) / 256, 4096));
+  // the sort buffer the slots do not use holds the queue of long segments
+  const int cur = (det_passes(p) - 1) & 1;
+  uint32_t* long_start = (uint32_t*)(ws + (cur ? p.det_k0 : p.det_k1));
+  uint32_t* long_cnt = (uint32_t*)(ws + p.det_cnt);
+  const uint32_t* keys = det_sorted_keys(p, ws);
+  const double* partial = (const double*)(ws + p.det_partial);
+  double* grad2d = (double*)(ws + p.lay.grad2d);
   ProfScope ps("det_reduce", s);
-  hipLaunchKernelGGL(det_reduce_kernel, dim3(std::max(1u, blocks)), dim3(256), 0, s, kb[cur],
-                     vb[cur], n_dev, (const double*)(ws + p.det_partial), p.cap,
-                     (double*)(ws + p.lay.grad2d), p.M);
+  hipLaunchKernelGGL(det_count_zero, dim3(1), dim3(64), 0, s, long_cnt);
+  hipLaunchKernelGGL(det_reduce_short, dim3(blocks), dim3(256), 0, s, keys, n_dev, partial, grad2d,
+                     p.M, long_start, long_cnt);
+  hipLaunchKernelGGL(det_reduce_long, dim3(1024), dim3(256), 0, s, keys, n_dev, partial, grad2d, p.M,
+                     (const uint32_t*)long_start, (const uint32_t*)long_cnt);
   return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ struct Plan {
          hist = 0, digit_tot = 0, scan_part = 0, span_owner = 0, span_cnt = 0, span_off = 0,
          chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, drect = 0, pmask = 0;
   // deterministic backward: per-entry sums [9][cap] and the pair-order sort
-  size_t det_partial = 0, det_k0 = 0, det_v0 = 0, det_k1 = 0, det_v1 = 0;
+  size_t det_partial = 0, det_k0 = 0, det_v0 = 0, det_k1 = 0, det_v1 = 0, det_cnt = 0;
   int64_t n_spans = 0;        // entries of span_owner: ceil(cap / kKeygenSpan) + 1
   int32_t K = 1;              // depth chunks
   std::vector<int64_t> chunk_pos;   // [K + 1] pair positions in depth order
@@ -262,7 +262,9 @@ hipError_t launch_densify_stats(const Plan& p, const ls_config* cfg, char* ws,
 hipError_t launch_densify_select(const ls_densify_params* prm, int64_t n, const float* scales,
                                  const float* opacity, const ls_densify_acc* acc, uint8_t* action,
                                  int64_t* counts, hipStream_t s);
+hipError_t launch_det_order(const Plan& p, char* ws, hipStream_t s);
 hipError_t launch_det_reduce(const Plan& p, char* ws, hipStream_t s);
+const uint32_t* det_slots(const Plan& p, char* ws);
 size_t loss_workspace_bytes(int64_t P, int C);
 hipError_t launch_loss(const int32_t* W, const int32_t* H, int C, const float* image,
                        const float* target, float* dL_dimage, double* loss, char* ws,

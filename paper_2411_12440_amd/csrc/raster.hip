@@ -454,7 +454,8 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
     RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
-    double* __restrict__ grad2d, double* __restrict__ partial, int64_t cap) {
+    double* __restrict__ grad2d, double* __restrict__ partial,
+    const uint32_t* __restrict__ det_slot) {
   constexpr int PPL = raster_ppl<TW, TH>();
   constexpr int NTB = raster_threads<TW, TH>();
   constexpr int NWB = NTB / 64;
@@ -662,14 +663,16 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     __syncthreads();
     if (tid < cnt) {
       if (partial) {
-        // deterministic mode: the entry's own slot (its position in the
-        // chunk-concatenated lists); the pair sums are formed afterwards
+        // deterministic mode: the entry's slot in pair order (from its
+        // position in the chunk-concatenated lists); the pair sums are
+        // formed afterwards
         const int32_t q = st.pos[tid];
         int cc = 0;
         while (cc + 1 < K && s_segpre[cc + 1] <= q) ++cc;
         const int64_t e = s_segbase[cc] + (q - s_segpre[cc]);
+        const int64_t slot = det_slot[e];
 #pragma unroll
-        for (int f = 0; f < kGrad2d; ++f) partial[(int64_t)f * cap + e] = s_acc[tid][f];
+        for (int f = 0; f < kGrad2d; ++f) partial[slot * kGrad2d + f] = s_acc[tid][f];
       } else {
         const int64_t m = (int64_t)st.m[tid];
 #pragma unroll
@@ -682,13 +685,12 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   }
 }
 
-// zero rows [0, n) of the deterministic mode's per-entry sums (row f at f * cap)
-__global__ void det_zero_kernel(double* __restrict__ partial, int64_t cap,
-                                const int64_t* __restrict__ n_dev) {
-  const int64_t n = *n_dev;
-  double* row = partial + (int64_t)blockIdx.y * cap;
+// zero the deterministic mode's per-entry sums of the n built entries
+// (entry-major: the nine sums of entry e at 9 e)
+__global__ void det_zero_kernel(double* __restrict__ partial, const int64_t* __restrict__ n_dev) {
+  const int64_t n = *n_dev * kGrad2d;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    row[i] = 0.0;
+    partial[i] = 0.0;
 }
 
 __global__ void zero_kernel(float* __restrict__ p, int64_t n) {
@@ -796,21 +798,24 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     const int npix = cfg->tile_w * cfg->tile_h;
     const int batch = cfg->batch ? cfg->batch : npix;
     double* partial = nullptr;
+    const uint32_t* det_slot = nullptr;
     if (cfg->deterministic && p.cap > 0) {
+      hipError_t e = launch_det_order(p, ws, s);
+      if (e != hipSuccess) return e;
+      det_slot = det_slots(p, ws);
       // entries the backward pass does not stage (culled, or past every
       // pixel's last contributor) keep zero sums
       partial = (double*)(ws + p.det_partial);
-      const unsigned blocks = (unsigned)std::min<int64_t>((p.cap + 255) / 256, 4096);
+      const unsigned blocks = (unsigned)std::min<int64_t>((kGrad2d * p.cap + 255) / 256, 8192);
       ProfScope ps("det_zero", s);
-      hipLaunchKernelGGL(det_zero_kernel, dim3(blocks, kGrad2d), dim3(256), 0, s, partial, p.cap,
-                         chunk_base + p.K);
+      hipLaunchKernelGGL(det_zero_kernel, dim3(blocks), dim3(256), 0, s, partial, chunk_base + p.K);
     }
     dim3 grid((unsigned)p.T);
     ProfScope ps("raster_bwd", s);
 #define LS_BWD(TW_, TH_, KF_)                                                                      \
   hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_>), grid, dim3(raster_threads<TW_, TH_>()), 0, \
                      s, cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,         \
-                     final_T, last, dL_dimage, dL_dalpha, grad2d, partial, p.cap)
+                     final_T, last, dL_dimage, dL_dalpha, grad2d, partial, det_slot)
 #define LS_BWD_K(TW_, TH_)                                                                         \
   switch (cfg->kernel) {                                                                           \
     case LS_KERNEL_GAUSSIAN: LS_BWD(TW_, TH_, LS_KERNEL_GAUSSIAN); break;                          \
@@ -827,7 +832,10 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
 #undef LS_BWD
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (partial && (e = launch_det_reduce(p, ws, s)) != hipSuccess) return e;
+  }
+  if (p.T > 0 && cfg->deterministic && p.cap > 0) {
+    hipError_t e = launch_det_reduce(p, ws, s);
+    if (e != hipSuccess) return e;
   }
   return launch_project_bwd(p, cfg, sp, ws, g, s);
 }
