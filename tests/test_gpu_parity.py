@@ -324,3 +324,38 @@ def test_deterministic_backward(chunks):
         p0 = int(fw.lay.pair_off[c])
         assert np.array_equal(one2d, g2d[:, p0:p0 + m1]), c
         pix += n
+
+
+def test_non_finite_splats_are_culled():
+    """Splats with a non-finite centre, scale or rotation touch no tile on
+    either side; the rest of the scene renders and differentiates as usual,
+    and the culled splats receive exactly zero gradient."""
+    say("case: non-finite centres, scales and rotations among 400 splats")
+    scene = scenes.make_scene(400, 321, -3.0, 0.5, 1)
+    bad = np.array([0, 1, 2, 3, 4, 5])
+    scene.means[0, 0] = np.nan
+    scene.means[1, 2] = np.inf
+    scene.means[2, 1] = -np.inf
+    scene.scales[3, 1] = np.inf
+    scene.quats[4, :] = np.nan
+    scene.scales[5, 0] = np.nan
+    cams = scenes.front_camera(96, 64)
+    off = np.array([0, scene.n])
+    ocfg, gkw = cfg_pair()
+    G = scenes.upstream_grad(cams, 7321)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    G = G * ~pixel_flags_to_image(fw.flag, cams)
+    g, grads = _run_fwd_bwd(scene, off, cams, gkw, G)
+    assert np.all(g["ntiles"][bad] == 0) and np.all(fw.ntiles[bad] == 0)
+    assert np.count_nonzero(g["ntiles"]) > 200
+    compare_binning(g, fw)
+    compare_forward(g, fw, cams)
+    assert np.all(np.isfinite(g["image"]))
+    go = render_backward(fw, scene, cams, G)
+    ok = np.ones(scene.n, bool)
+    ok[bad] = False
+    for k, v in grads.items():
+        rows = v.T if v.ndim == 2 else (v.transpose(2, 0, 1) if v.ndim == 3 else v)
+        ref = go[k]
+        assert np.all(rows[bad] == 0.0), k
+        assert_close(f"d_{k}", rows[ok].astype(np.float64), ref[ok])
