@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 
 #include "internal.h"
@@ -26,6 +28,13 @@ static ls_status hip_fail(hipError_t e, const char* where) {
 }
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// One roctx range per entry point (visible to rocprofv3 --marker-trace; a
+// no-op without a tool attached).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+};
 
 static bool tile_shape_ok(int w, int h) {
   return (w == 16 && h == 16) || (w == 16 && h == 8) || (w == 8 && h == 8) || (w == 32 && h == 8);
@@ -256,6 +265,7 @@ ls_status ls_workspace_layout(const ls_config* cfg, const ls_cameras* cams, int6
 
 ls_status ls_project(const ls_config* cfg, const ls_splats* sp, const ls_cameras* cams, void* ws,
                      size_t ws_bytes, int64_t cap, void* stream) {
+  Range range("ls_project");
   Plan p;
   ls_status st = make_plan(cfg, cams, cap, &p);
   if (st != LS_OK) return st;
@@ -272,6 +282,7 @@ ls_status ls_project(const ls_config* cfg, const ls_splats* sp, const ls_cameras
 
 ls_status ls_bin_sort(const ls_config* cfg, const ls_cameras* cams, void* ws, size_t ws_bytes,
                       int64_t cap, void* stream) {
+  Range range("ls_bin_sort");
   Plan p;
   ls_status st = make_plan(cfg, cams, cap, &p);
   if (st != LS_OK) return st;
@@ -284,6 +295,7 @@ ls_status ls_bin_sort(const ls_config* cfg, const ls_cameras* cams, void* ws, si
 ls_status ls_rasterize_fwd(const ls_config* cfg, const ls_cameras* cams, void* ws,
                            size_t ws_bytes, int64_t cap, float* image, float* final_T,
                            int32_t* last, void* stream) {
+  Range range("ls_rasterize_fwd");
   Plan p;
   ls_status st = make_plan(cfg, cams, cap, &p);
   if (st != LS_OK) return st;
@@ -298,6 +310,7 @@ ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* sp, const ls_c
                            void* ws, size_t ws_bytes, int64_t cap, const float* final_T,
                            const int32_t* last, const float* dL_dimage, const float* dL_dalpha,
                            const ls_grads* g, void* stream) {
+  Range range("ls_rasterize_bwd");
   Plan p;
   ls_status st = make_plan(cfg, cams, cap, &p);
   if (st != LS_OK) return st;
@@ -323,6 +336,7 @@ ls_status ls_loss_workspace_size(const ls_cameras* cams, size_t* bytes) {
 
 ls_status ls_loss(const ls_cameras* cams, const float* image, const float* target,
                   float* dL_dimage, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  Range range("ls_loss");
   int64_t P = 0;
   ls_status st = check_loss_cams(cams, &P);
   if (st != LS_OK) return st;
@@ -340,6 +354,7 @@ ls_status ls_loss(const ls_cameras* cams, const float* image, const float* targe
 
 ls_status ls_adam(const ls_adam_params* prm, int64_t n, float* param, const float* grad,
                   float* m, float* v, void* stream) {
+  Range range("ls_adam");
   if (!prm) return fail(LS_ERR_INVALID_ARG, "prm is NULL");
   if (n < 0) return fail(LS_ERR_INVALID_ARG, "n must be >= 0");
   if (prm->step < 1) return fail(LS_ERR_INVALID_ARG, "step must be >= 1");
@@ -355,6 +370,7 @@ ls_status ls_adam(const ls_adam_params* prm, int64_t n, float* param, const floa
 ls_status ls_densify_stats(const ls_config* cfg, const ls_cameras* cams, void* ws,
                            size_t ws_bytes, int64_t cap, const ls_densify_acc* acc,
                            void* stream) {
+  Range range("ls_densify_stats");
   Plan p;
   ls_status st = make_plan(cfg, cams, cap, &p);
   if (st != LS_OK) return st;
@@ -369,6 +385,7 @@ ls_status ls_densify_stats(const ls_config* cfg, const ls_cameras* cams, void* w
 ls_status ls_densify_select(const ls_densify_params* prm, int64_t n, const float* scales,
                             const float* opacity, const ls_densify_acc* acc, uint8_t* action,
                             int64_t* counts, void* stream) {
+  Range range("ls_densify_select");
   if (!prm) return fail(LS_ERR_INVALID_ARG, "prm is NULL");
   if (n < 0) return fail(LS_ERR_INVALID_ARG, "n must be >= 0");
   const double th[7] = {prm->grad_threshold, prm->grow_scale2d, prm->grow_scale3d,
