@@ -164,12 +164,13 @@ __global__ __launch_bounds__(256) void ssim_moments_kernel(
         const double a2 = 2.0 * (m[4][q] - mx * my) + kC2;
         const double b1 = mx * mx + my * my + kC1;
         const double b2 = (m[2][q] - mx * mx) + (m[3][q] - my * my) + kC2;
-        const double d = b1 * b2;
-        const double S = a1 * a2 / d;
+        // one division: 1/d with d = b1 b2, and 1/b2 = b1/d
+        const double inv_d = 1.0 / (b1 * b2);
+        const double S = a1 * a2 * inv_d;
         const int64_t o = (int64_t)py * W + px;
-        cm[o] = (2.0 * my * (a2 - a1) - 2.0 * mx * S * (b2 - b1)) / d;
-        cm[t.plane + o] = -S / b2;
-        cm[2 * t.plane + o] = 2.0 * a1 / d;
+        cm[o] = (2.0 * my * (a2 - a1) - 2.0 * mx * S * (b2 - b1)) * inv_d;
+        cm[t.plane + o] = -S * (b1 * inv_d);
+        cm[2 * t.plane + o] = 2.0 * a1 * inv_d;
         const double df = (double)cx[q] - (double)cy[q];
         ss += S;
         s1 += fabs(df);
