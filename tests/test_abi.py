@@ -183,3 +183,25 @@ def test_training_stage_arguments_checked():
     cams = _cams()
     assert lib.ls_densify_stats(C.byref(cfg), C.byref(cams.c), None, 0, 0, C.byref(acc),
                                 None) == -5
+
+
+def test_header_is_plain_c():
+    """include/lsplat.h is a C header: it compiles as strict C99 (and C++)."""
+    import shutil
+    import subprocess
+    import tempfile
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    src = ('#include "lsplat.h"\n'
+           'int main(void) { ls_config c; ls_densify_acc a; ls_adam_params p;\n'
+           '  (void)c; (void)a; (void)p; return LSPLAT_VERSION > 0 ? 0 : 1; }\n')
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "h.c")
+        with open(f, "w") as fh:
+            fh.write(src)
+        for lang, std in (("c", "c99"), ("c++", "c++17")):
+            r = subprocess.run([gcc, "-x", lang, f"-std={std}", "-Wall", "-Wextra", "-pedantic",
+                                "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"), f],
+                               capture_output=True, text=True)
+            assert r.returncode == 0, r.stderr
