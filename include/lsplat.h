@@ -305,7 +305,9 @@ ls_status ls_rasterize_fwd(const ls_config* cfg, const ls_cameras* cams, void* w
 /*
  * Backward pass of ls_rasterize_fwd and ls_project.  Walks each tile's list
  * back to front from `last`, recovering the transmittance by division
- * (T_i = T_{i+1} / (1 - alpha_i)), accumulates per-pair 2D gradients (with
+ * (T_i = T_{i+1} / (1 - alpha_i)) from the FP64 final transmittance the
+ * forward call keeps in the workspace (final_T is its FP32 rounding, which
+ * can underflow when t_min = 0), accumulates per-pair 2D gradients (with
  * adaptive gradient scaling, Eq. 13-14, when cfg->ags), then applies the
  * chain rule through the projection and sums over cameras.
  * final_T, last  from the forward call on the same workspace and settings.

@@ -186,6 +186,7 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
     p->state = take(32 * (size_t)p->P);
     p->done = take((size_t)p->P);
   }
+  p->t64 = take(8 * (size_t)p->P);
   if (cfg->deterministic) {
     p->det_partial = take(8 * (size_t)kGrad2d * CAP);
     p->det_k0 = take(4 * CAP);

@@ -64,6 +64,7 @@ struct Plan {
          chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, drect = 0, pmask = 0;
   // deterministic backward: per-entry sums [9][cap] and the pair-order sort
   size_t det_partial = 0, det_k0 = 0, det_v0 = 0, det_k1 = 0, det_v1 = 0, det_cnt = 0;
+  size_t t64 = 0;             // FP64 final transmittance [P], forward -> backward
   int64_t n_spans = 0;        // entries of span_owner: ceil(cap / kKeygenSpan) + 1
   int32_t K = 1;              // depth chunks
   std::vector<int64_t> chunk_pos;   // [K + 1] pair positions in depth order

@@ -316,7 +316,7 @@ void raster_fwd_kernel(
     const ProjRec* __restrict__ proj, int64_t M, int batch, RasterParams rp,
     double4* __restrict__ state, uint8_t* __restrict__ done_px, uint32_t* __restrict__ alive,
     float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ last,
-    uint32_t* __restrict__ tile_contrib) {
+    uint32_t* __restrict__ tile_contrib, double* __restrict__ t64) {
   constexpr int PPL = raster_ppl<TW, TH>();
   constexpr int NTB = raster_threads<TW, TH>();
   constexpr int NWB = NTB / 64;
@@ -424,6 +424,7 @@ void raster_fwd_kernel(
     image[ib + plane] = (float)(cg[j] + T[j] * (double)rp.bg1);
     image[ib + 2 * plane] = (float)(cb[j] + T[j] * (double)rp.bg2);
     final_T[pix[j]] = (float)T[j];
+    t64[pix[j]] = T[j];   // the backward pass starts from the FP64 value
     last[pix[j]] = lastc[j];
     if (K > 1 && c < K - 1) {
       state[pix[j]] = make_double4(T[j], cr[j], cg[j], cb[j]);
@@ -452,7 +453,7 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all,
     int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
-    RasterParams rp, const float* __restrict__ final_T, const int32_t* __restrict__ last,
+    RasterParams rp, const double* __restrict__ t64, const int32_t* __restrict__ last,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
     double* __restrict__ grad2d, double* __restrict__ partial,
     const uint32_t* __restrict__ det_slot) {
@@ -516,7 +517,9 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
       const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
       const int64_t plane = (int64_t)ci.W * ci.H;
       const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
-      T[j] = final_T[pix];
+      // FP64: with t_min = 0 a pixel's final transmittance can fall below
+      // the FP32 range, and every T_i is recovered from it by division
+      T[j] = t64[pix];
       const int32_t l = last[pix];
       mylast[j] = l < 0 ? 0 : (l > len ? (int32_t)len : l);
       G0[j] = dL_dimage[ib];
@@ -758,7 +761,7 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
 #define LS_FWD(TW_, TH_, KF_)                                                                      \
   hipLaunchKernelGGL((raster_fwd_kernel<TW_, TH_, KF_>), grid, dim3(raster_threads<TW_, TH_>()), 0, \
                      s, cams, p.C, ranges, p.T, c, p.K, chunk_base, vals, proj, p.M, batch, rp,      \
-                     state, done, alive, image, final_T, last, tile_contrib)
+                     state, done, alive, image, final_T, last, tile_contrib, (double*)(ws + p.t64))
 #define LS_FWD_K(TW_, TH_)                                                                         \
   switch (cfg->kernel) {                                                                           \
     case LS_KERNEL_GAUSSIAN: LS_FWD(TW_, TH_, LS_KERNEL_GAUSSIAN); break;                          \
@@ -815,7 +818,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
 #define LS_BWD(TW_, TH_, KF_)                                                                      \
   hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_>), grid, dim3(raster_threads<TW_, TH_>()), 0, \
                      s, cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,         \
-                     final_T, last, dL_dimage, dL_dalpha, grad2d, partial, det_slot)
+                     (const double*)(ws + p.t64), last, dL_dimage, dL_dalpha, grad2d, partial, det_slot)
 #define LS_BWD_K(TW_, TH_)                                                                         \
   switch (cfg->kernel) {                                                                           \
     case LS_KERNEL_GAUSSIAN: LS_BWD(TW_, TH_, LS_KERNEL_GAUSSIAN); break;                          \
