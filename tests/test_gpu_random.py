@@ -3,7 +3,8 @@ size, splat-size distribution, SH degree, camera set (one to four cameras of
 random size, one or two scenes), tile shape, LDS batch, depth chunks, kernel,
 AGS reading, strictness, background and the deterministic flag are drawn,
 and the library is compared with the oracle at the usual bars (binning
-integers bit-exact, composite and gradients within 1e-5)."""
+integers bit-exact, composite and gradients within 1e-5), together with the
+densification statistics of the same backward pass."""
 from __future__ import annotations
 
 import numpy as np
@@ -75,3 +76,18 @@ def test_random_configuration(seed):
     torch.cuda.synchronize()
     go = render_backward(fw, scene, cams, G)
     compare_grads({k: v.cpu().numpy().astype(np.float64) for k, v in grads.items()}, go, scene)
+    # densification statistics of the same backward pass
+    from paper_2411_12440_amd import binding as B
+    from tests.test_gpu_train import _oracle_stats, _within_ulp
+    from oracle import densify as odens
+    N = scene.n
+    acc_t = [torch.zeros(N, dtype=torch.float32, device="cuda"),
+             torch.zeros(N, dtype=torch.int32, device="cuda"),
+             torch.zeros(N, dtype=torch.float32, device="cuda")]
+    B.ls_densify_stats(rast.cfg, rast.cams, rast.ws, rast.capacity, B.densify_acc(*acc_t))
+    torch.cuda.synchronize()
+    oacc = _oracle_stats(fw, go, cams, ocfg, odens.new_acc(N))
+    assert np.array_equal(acc_t[1].cpu().numpy(), oacc["count"])
+    _within_ulp(acc_t[2].cpu().numpy(), oacc["max_extent"], 2, "max_extent")
+    from tests.gpu_helpers import assert_close
+    assert_close("densify grad", acc_t[0].cpu().numpy().astype(np.float64), oacc["grad"])
