@@ -80,23 +80,31 @@ def make_workload(n_splats, views):
 # --------------------------------------------------------------------------
 
 def kernel_cost(name, w):
-    """(bound, amount per launch, unit) for the kernels we can price."""
+    """(bound, amount per step, unit) for the kernels we can price.  Sort
+    passes: 4 of 8 bits over the M depth keys, tile_passes over the entries."""
     N, M, n, K, Q, Qc = w["N"], w["M"], w["n_built"], w["K"], w["Q"], w["Qc"]
+    tp = w["tile_passes"]
     splat_bytes = 44 + 12 * K
     if name == "tilesort_downsweep":
-        return "hbm", 16.0 * n, "B"
+        return "hbm", 16.0 * n * tp, "B"
     if name == "tilesort_upsweep":
-        return "hbm", 4.0 * n, "B"
+        return "hbm", 4.0 * n * tp, "B"
     if name == "presort_downsweep":
-        return "hbm", 16.0 * M, "B"
+        return "hbm", 16.0 * M * 4, "B"
     if name == "presort_upsweep":
-        return "hbm", 4.0 * M, "B"
+        return "hbm", 4.0 * M * 4, "B"
     if name in ("keygen", "keygen_write"):
         return "hbm", 8.0 * n + 20.0 * M, "B"
     if name == "project":
         return "hbm", float(splat_bytes) * N + 80.0 * M, "B"
     if name == "project_bwd":
-        return "hbm", float(splat_bytes - 4) * N + 36.0 * M + float(splat_bytes) * N, "B"
+        # centre, scale, rotation read and their gradients with the opacity's
+        # written per splat; six FP64 2D-gradient fields read per pair
+        return "hbm", 84.0 * N + 48.0 * M, "B"
+    if name == "project_bwd_sh":
+        # SH read and its gradient written, centre read and its gradient
+        # updated per splat; three FP64 colour-gradient fields read per pair
+        return "hbm", (24.0 * K + 36.0) * N + 24.0 * M, "B"
     # Compositing: every (pixel, splat) pair up to the pixel's last contributor
     # (Q of them) evaluates D'^2 (5 FMA = 10 flops); each contributing pair (Qc)
     # then costs 13 flops forward (sqrt, alpha, T (1 - alpha), alpha T, three
@@ -439,7 +447,10 @@ def main():
         log(f"bench: training stages {train}")
 
     # ---- roofline of the dominant kernel --------------------------------------
-    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q, Qc=Qc)
+    T_tiles = int(rast.layout.n_tiles)
+    tile_passes = max(1, ((T_tiles - 1).bit_length() + 7) // 8)
+    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q, Qc=Qc,
+             tile_passes=tile_passes)
     kernels = []
     for name, launches, total in ktimes:
         row = dict(kernel=name, launches=launches, avg_ms=round(total / launches, 4),
