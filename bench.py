@@ -56,6 +56,12 @@ def parse():
     ap.add_argument("--splats", type=int, default=3_200_000)
     ap.add_argument("--ags", type=int, default=1)
     ap.add_argument("--depth-chunks", type=int, default=7)
+    ap.add_argument("--tune", type=int, default=1,
+                    help="1: tile shape, LDS batch and depth chunks from the autotuner (timed "
+                         "before the measurement, cached per device and workload); 0: 16x16 "
+                         "tiles, one splat per thread per batch, --depth-chunks")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="LDS batch with --tune 0 (0: one splat per thread)")
     ap.add_argument("--deterministic", type=int, default=0,
                     help="1: the bitwise-reproducible backward (per-entry sums, pair sort)")
     ap.add_argument("--no-per-view", action="store_true")
@@ -286,9 +292,19 @@ def main():
     scene, cams = make_workload(args.splats, args.views)
     sp = scene_to_device(scene, dev)
     G_all = torch.from_numpy(S.upstream_grad(cams, 7004)).to(dev)
-    cfgkw = dict(sh_degree=3, ags=bool(args.ags), depth_chunks=args.depth_chunks,
-                 deterministic=bool(args.deterministic))
     off = np.array([0, scene.n])
+    settings = dict(tile_w=16, tile_h=16, batch=args.batch, depth_chunks=args.depth_chunks)
+    tuned = None
+    if args.tune:
+        from paper_2411_12440_amd import autotune
+        log("bench: autotuning tile shape, LDS batch and depth chunks")
+        tuner = autotune.Autotuner()
+        settings = tuner.choose(cams, off, sp, G_all, 3, ags=bool(args.ags))
+        tuned = tuner.table.get(autotune.tune_key(torch.cuda.get_device_name(dev), scene.n,
+                                                  cams, 3))
+        log(f"bench: tuned settings {settings}")
+    cfgkw = dict(sh_degree=3, ags=bool(args.ags), deterministic=bool(args.deterministic),
+                 **settings)
     P = int(sum(int(w) * int(h) for w, h in zip(cams.width, cams.height)))
 
     # ---- batched path -------------------------------------------------------
@@ -503,11 +519,14 @@ def main():
         "config": {"workload": "3.2M splats SH3, log-scale N(-4,1), 8 views 1920x1080 on a "
                                "radius-4 sphere, fwd+bwd, batched",
                    "views": cams.n, "pixels_per_step": P, "n_isect": n_isect,
-                   "entries_built": n_built, "depth_chunks": args.depth_chunks,
+                   "entries_built": n_built, "depth_chunks": settings["depth_chunks"],
                    "chunk_entries": chunk_entries,
                    "pairs_to_last": Q, "contributing_pairs": Qc, "ags": bool(args.ags),
                    "deterministic": bool(args.deterministic),
-                   "tile": "16x16",
+                   "tile": f"{settings['tile_w']}x{settings['tile_h']}",
+                   "lds_batch": settings["batch"],
+                   "autotuned": bool(args.tune),
+                   "tuning": None if tuned is None else tuned.get("results"),
                    "parallelism": "single GPU"},
         "eager": {"ms_per_step": round(ms_eager, 4),
                   "value": round(P / (ms_eager * 1e-3) / 1e6, 3),
