@@ -97,3 +97,68 @@ def test_graph_replay_matches_eager(chunks):
     got = {k: v.double().cpu().numpy() for k, v in grads.items()}
     compare_grads(got, render_backward(fw, scene, cams, G2), scene)
     say("  replays equal the eager results")
+
+
+def test_training_stages_in_a_graph():
+    """The loss, an Adam step and the densification decision captured into
+    one HIP graph: each replay (eager work and a host synchronisation between
+    replays) gives the eager results.  The image gradient, Adam and the
+    decision use no float atomics (bit for bit); the per-camera loss sums do
+    (to 1e-14)."""
+    import torch
+    from paper_2411_12440_amd import binding as B
+    say("case: loss + Adam + densification decision captured in a graph")
+    widths, heights = [64, 37, 90], [48, 53, 30]
+    img, tgt = scenes.image_pair(widths, heights, seed=61)
+    cams = B.CamerasHost(None, None, np.array(widths), np.array(heights), np.zeros(3),
+                         np.array([0, 0]))
+    ti, tt = torch.from_numpy(img).cuda(), torch.from_numpy(tgt).cuda()
+    lws = torch.empty(B.ls_loss_workspace_size(cams), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(62)
+    n = 10007
+    p0 = torch.from_numpy(rng.normal(size=n).astype(np.float32)).cuda()
+    g0 = torch.from_numpy(rng.normal(size=n).astype(np.float32)).cuda()
+    scales = torch.from_numpy(np.exp(rng.normal(-5, 1.5, (3, n))).astype(np.float32)).cuda()
+    opac = torch.from_numpy(rng.uniform(0, 0.1, n).astype(np.float32)).cuda()
+    acc_g = torch.from_numpy((rng.uniform(0, 1e-3, n)).astype(np.float32)).cuda()
+    acc_c = torch.from_numpy(rng.integers(0, 4, n).astype(np.int32)).cuda()
+    acc_e = torch.from_numpy(rng.uniform(0, 0.3, n).astype(np.float32)).cuda()
+    acc = B.densify_acc(acc_g, acc_c, acc_e)
+    prm = B.densify_params(0.05, grow2d=True, prune_big=True)
+
+    def fresh():
+        return dict(dimg=torch.zeros_like(ti), loss=torch.zeros(3, dtype=torch.float64, device="cuda"),
+                    p=p0.clone(), m=torch.zeros_like(p0), v=torch.zeros_like(p0),
+                    action=torch.zeros(n, dtype=torch.uint8, device="cuda"),
+                    counts=torch.zeros(3, dtype=torch.int64, device="cuda"))
+
+    def stages(o, stream=None):
+        B.ls_loss(cams, ti, tt, o["dimg"], o["loss"], lws, stream)
+        B.ls_adam(B.adam_params(0.01, 3), o["p"], g0, o["m"], o["v"], stream)
+        B.ls_densify_select(prm, n, scales, opac, acc, o["action"], o["counts"], stream)
+
+    ref = fresh()
+    stages(ref)
+    torch.cuda.synchronize()
+    cap = fresh()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        stages(cap, side.cuda_stream)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        stages(cap, torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        for k in ("p", "m", "v"):      # Adam updates in place: start each replay from the state
+            cap[k].copy_(fresh()[k])  # the eager reference started from
+        cap["dimg"].zero_()
+        cap["action"].zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()     # eager work between replays
+        for k in ("dimg", "p", "m", "v", "action", "counts"):
+            assert torch.equal(cap[k], ref[k]), f"replay {rep}: {k} differs"
+        assert torch.allclose(cap["loss"], ref["loss"], rtol=1e-14, atol=0), f"replay {rep}: loss"
