@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 160
+#define LSPLAT_VERSION 170
 
 typedef enum {
   LS_OK = 0,
@@ -378,6 +378,18 @@ typedef struct ls_adam_params {
 
 ls_status ls_adam(const ls_adam_params* prm, int64_t n, float* param, const float* grad,
                   float* m, float* v, void* stream);
+
+/*
+ * ls_adam with the step t read from device memory when the kernels run
+ * (step_dev: one int64, >= 1; prm->step is not used), so that a captured
+ * HIP graph can replay successive steps: the caller advances *step_dev
+ * between replays, for example with a small kernel inside the graph.  Other
+ * arguments, checks and arithmetic as ls_adam (the bias corrections are
+ * formed on the device in FP64).
+ */
+ls_status ls_adam_device_step(const ls_adam_params* prm, const int64_t* step_dev, int64_t n,
+                              float* param, const float* grad, float* m, float* v,
+                              void* stream);
 
 /*
  * Densification statistics (the per-splat quantities 3DGS adaptive density

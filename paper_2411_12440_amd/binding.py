@@ -111,6 +111,8 @@ def _load() -> C.CDLL:
                      C.c_size_t, C.c_void_p], C.c_int),
         "ls_adam": ([P(AdamParams), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p], C.c_int),
+        "ls_adam_device_step": ([P(AdamParams), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
         "ls_densify_stats": ([P(Config), P(Cams), C.c_void_p, C.c_size_t, C.c_int64,
                               P(DensifyAcc), C.c_void_p], C.c_int),
         "ls_densify_select": ([P(DensifyParams), C.c_int64, C.c_void_p, C.c_void_p,
@@ -128,7 +130,7 @@ def _load() -> C.CDLL:
 LIB = _load()
 EXPORTS = ("ls_version", "ls_last_error", "ls_workspace_size", "ls_workspace_layout",
            "ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd",
-           "ls_loss_workspace_size", "ls_loss", "ls_adam", "ls_densify_stats",
+           "ls_loss_workspace_size", "ls_loss", "ls_adam", "ls_adam_device_step", "ls_densify_stats",
            "ls_densify_select", "ls_profile_enable", "ls_profile_read")
 
 
@@ -244,6 +246,11 @@ def adam_params(lr, step, beta1=0.9, beta2=0.999, eps=1e-15) -> AdamParams:
 def ls_adam(prm: AdamParams, param, grad, m, v, stream=None):
     _check(LIB.ls_adam(C.byref(prm), param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
                        _stream(stream)))
+
+
+def ls_adam_device_step(prm: AdamParams, step_dev, param, grad, m, v, stream=None):
+    _check(LIB.ls_adam_device_step(C.byref(prm), _ptr(step_dev), param.numel(), _ptr(param),
+                                   _ptr(grad), _ptr(m), _ptr(v), _stream(stream)))
 
 
 def densify_acc(grad, count, max_extent) -> DensifyAcc:

@@ -353,18 +353,37 @@ ls_status ls_loss(const ls_cameras* cams, const float* image, const float* targe
   return LS_OK;
 }
 
-ls_status ls_adam(const ls_adam_params* prm, int64_t n, float* param, const float* grad,
-                  float* m, float* v, void* stream) {
-  Range range("ls_adam");
+static ls_status check_adam(const ls_adam_params* prm, bool need_step, int64_t n, float* param,
+                            const float* grad, float* m, float* v) {
   if (!prm) return fail(LS_ERR_INVALID_ARG, "prm is NULL");
   if (n < 0) return fail(LS_ERR_INVALID_ARG, "n must be >= 0");
-  if (prm->step < 1) return fail(LS_ERR_INVALID_ARG, "step must be >= 1");
+  if (need_step && prm->step < 1) return fail(LS_ERR_INVALID_ARG, "step must be >= 1");
   if (!(prm->beta1 >= 0.0 && prm->beta1 < 1.0) || !(prm->beta2 >= 0.0 && prm->beta2 < 1.0))
     return fail(LS_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
   if (!(prm->eps >= 0.0) || !(prm->lr == prm->lr)) return fail(LS_ERR_INVALID_ARG, "eps must be >= 0, lr finite");
   if (n > 0 && (!param || !grad || !m || !v)) return fail(LS_ERR_INVALID_ARG, "param/grad/m/v is NULL");
-  hipError_t e = launch_adam(prm, n, param, grad, m, v, (hipStream_t)stream);
+  return LS_OK;
+}
+
+ls_status ls_adam(const ls_adam_params* prm, int64_t n, float* param, const float* grad,
+                  float* m, float* v, void* stream) {
+  Range range("ls_adam");
+  ls_status st = check_adam(prm, true, n, param, grad, m, v);
+  if (st != LS_OK) return st;
+  hipError_t e = launch_adam(prm, nullptr, n, param, grad, m, v, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "adam");
+  return LS_OK;
+}
+
+ls_status ls_adam_device_step(const ls_adam_params* prm, const int64_t* step_dev, int64_t n,
+                              float* param, const float* grad, float* m, float* v,
+                              void* stream) {
+  Range range("ls_adam_device_step");
+  if (!step_dev) return fail(LS_ERR_INVALID_ARG, "step_dev is NULL");
+  ls_status st = check_adam(prm, false, n, param, grad, m, v);
+  if (st != LS_OK) return st;
+  hipError_t e = launch_adam(prm, step_dev, n, param, grad, m, v, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "adam_device_step");
   return LS_OK;
 }
 

@@ -256,8 +256,8 @@ hipError_t launch_raster_fwd(const Plan& p, const ls_config* cfg, char* ws, floa
                              float* final_T, int32_t* last, hipStream_t s);
 hipError_t launch_project_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                               const ls_grads* g, hipStream_t s);
-hipError_t launch_adam(const ls_adam_params* prm, int64_t n, float* p, const float* g, float* m,
-                       float* v, hipStream_t s);
+hipError_t launch_adam(const ls_adam_params* prm, const int64_t* step_dev, int64_t n, float* p,
+                       const float* g, float* m, float* v, hipStream_t s);
 hipError_t launch_densify_stats(const Plan& p, const ls_config* cfg, char* ws,
                                 const ls_densify_acc* acc, hipStream_t s);
 hipError_t launch_densify_select(const ls_densify_params* prm, int64_t n, const float* scales,

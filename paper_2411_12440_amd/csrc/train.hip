@@ -22,6 +22,15 @@ struct AdamCoef {
   double b1, b2, eps;
 };
 
+// bias corrections of step *step_dev (the graph-replayable variant reads the
+// step from device memory; every thread forms the same two coefficients)
+__device__ __forceinline__ AdamCoef adam_coef_dev(AdamCoef k, double lr, const int64_t* step_dev) {
+  const double t = (double)*step_dev;
+  k.lr_bc1 = lr / (1.0 - pow(k.b1, t));
+  k.inv_bc2 = 1.0 / (1.0 - pow(k.b2, t));
+  return k;
+}
+
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, const AdamCoef& k) {
   const double gd = g;
   const double md = k.b1 * (double)m + (1.0 - k.b1) * gd;
@@ -35,7 +44,8 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
 // path only when every pointer is 16-byte aligned
 __global__ __launch_bounds__(kTrainThreads) void adam_vec4_kernel(
     int64_t n4, float4* __restrict__ p, const float4* __restrict__ g, float4* __restrict__ m,
-    float4* __restrict__ v, AdamCoef k) {
+    float4* __restrict__ v, AdamCoef k, double lr, const int64_t* __restrict__ step_dev) {
+  if (step_dev) k = adam_coef_dev(k, lr, step_dev);
   const int64_t stride = (int64_t)gridDim.x * kTrainThreads;
   for (int64_t i = (int64_t)blockIdx.x * kTrainThreads + threadIdx.x; i < n4; i += stride) {
     float4 pp = p[i], mm = m[i], vv = v[i];
@@ -52,7 +62,9 @@ __global__ __launch_bounds__(kTrainThreads) void adam_vec4_kernel(
 
 __global__ __launch_bounds__(kTrainThreads) void adam_kernel(
     int64_t lo, int64_t n, float* __restrict__ p, const float* __restrict__ g,
-    float* __restrict__ m, float* __restrict__ v, AdamCoef k) {
+    float* __restrict__ m, float* __restrict__ v, AdamCoef k, double lr,
+    const int64_t* __restrict__ step_dev) {
+  if (step_dev) k = adam_coef_dev(k, lr, step_dev);
   const int64_t stride = (int64_t)gridDim.x * kTrainThreads;
   for (int64_t i = lo + (int64_t)blockIdx.x * kTrainThreads + threadIdx.x; i < n; i += stride) {
     float pp = p[i], mm = m[i], vv = v[i];
@@ -165,11 +177,11 @@ __global__ __launch_bounds__(kTrainThreads) void densify_select_kernel(
 
 }  // namespace
 
-hipError_t launch_adam(const ls_adam_params* prm, int64_t n, float* p, const float* g, float* m,
-                       float* v, hipStream_t s) {
+hipError_t launch_adam(const ls_adam_params* prm, const int64_t* step_dev, int64_t n, float* p,
+                       const float* g, float* m, float* v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   AdamCoef k;
-  const double t = (double)prm->step;
+  const double t = (double)(step_dev ? 1 : prm->step);   // replaced in the kernel
   k.lr_bc1 = prm->lr / (1.0 - pow(prm->beta1, t));
   k.inv_bc2 = 1.0 / (1.0 - pow(prm->beta2, t));
   k.b1 = prm->beta1;
@@ -181,12 +193,12 @@ hipError_t launch_adam(const ls_adam_params* prm, int64_t n, float* p, const flo
   if (aligned && n >= 4) {
     const int64_t n4 = n / 4;
     hipLaunchKernelGGL(adam_vec4_kernel, dim3(grid_for(n4)), dim3(kTrainThreads), 0, s, n4,
-                       (float4*)p, (const float4*)g, (float4*)m, (float4*)v, k);
+                       (float4*)p, (const float4*)g, (float4*)m, (float4*)v, k, prm->lr, step_dev);
     done = n4 * 4;
   }
   if (done < n)
     hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n - done)), dim3(kTrainThreads), 0, s, done, n, p,
-                       g, m, v, k);
+                       g, m, v, k, prm->lr, step_dev);
   return hipGetLastError();
 }
 

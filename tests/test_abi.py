@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(B.EXPORTS) == set(declared_functions())
-    assert B.ls_version() == 160
+    assert B.ls_version() == 170
 
 
 def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):

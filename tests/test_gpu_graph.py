@@ -162,3 +162,49 @@ def test_training_stages_in_a_graph():
         for k in ("dimg", "p", "m", "v", "action", "counts"):
             assert torch.equal(cap[k], ref[k]), f"replay {rep}: {k} differs"
         assert torch.allclose(cap["loss"], ref["loss"], rtol=1e-14, atol=0), f"replay {rep}: loss"
+
+
+def test_adam_steps_replayed_from_a_graph():
+    """ls_adam_device_step and the step increment captured together: three
+    replays are three successive Adam steps (t = 1, 2, 3), as eager ls_adam
+    calls give them (within 1 FP32 ulp: host and device form the bias
+    corrections separately)."""
+    import torch
+    from paper_2411_12440_amd import binding as B
+    say("case: Adam with a device-side step count replayed from a graph")
+    rng = np.random.default_rng(71)
+    n = 20011
+    p0 = rng.normal(size=n).astype(np.float32)
+    grads = [rng.normal(size=n).astype(np.float32) for _ in range(3)]
+    # eager reference
+    pe, me, ve = (torch.from_numpy(a).cuda() for a in (p0, np.zeros(n, np.float32),
+                                                       np.zeros(n, np.float32)))
+    for t in range(1, 4):
+        B.ls_adam(B.adam_params(0.01, t), pe, torch.from_numpy(grads[t - 1]).cuda(), me, ve)
+    torch.cuda.synchronize()
+    # graph: the gradient buffer is refilled in place before each replay
+    pg, mg, vg = (torch.from_numpy(a).cuda() for a in (p0, np.zeros(n, np.float32),
+                                                       np.zeros(n, np.float32)))
+    gbuf = torch.zeros(n, dtype=torch.float32, device="cuda")
+    step = torch.ones(1, dtype=torch.int64, device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):      # warm the allocator off the capture stream
+        tmp = step + 0
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        B.ls_adam_device_step(B.adam_params(0.01, 0), step, pg, gbuf, mg, vg,
+                              torch.cuda.current_stream().cuda_stream)
+        step.add_(1)
+    for t in range(1, 4):
+        gbuf.copy_(torch.from_numpy(grads[t - 1]).cuda())
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+    assert int(step.item()) == 4
+    for name, a, b in (("param", pg, pe), ("m", mg, me), ("v", vg, ve)):
+        x, y = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(x - y) <= 2.0 ** -23 * np.abs(y) + 1e-38), name
+    del tmp

@@ -218,3 +218,21 @@ def test_densify_stats(kernel, chunks):
     assert (got_c > c0).sum() > N // 4, "too few visible splats for a meaningful test"
     _within_ulp(de.cpu().numpy(), oacc["max_extent"], 2, "max_extent")
     assert_close("densify grad", dg.cpu().numpy().astype(np.float64), oacc["grad"])
+
+
+@pytest.mark.parametrize("n,t,offset", [(1000003, 50, 0), (4099, 1, 1)])
+def test_adam_device_step(n, t, offset):
+    """The step read from device memory gives the host-step result."""
+    import torch
+    from paper_2411_12440_amd import binding as B
+    say(f"adam device step: n={n} t={t} offset={offset}")
+    p, g, m, v = _adam_inputs(n, t, 200 + t)
+    dev = [torch.from_numpy(np.concatenate([np.zeros(offset, np.float32), a])).cuda()[offset:]
+           for a in (p, g, m, v)]
+    step = torch.tensor([t], dtype=torch.int64, device="cuda")
+    B.ls_adam_device_step(B.adam_params(1e-3, 0), step, *dev)
+    torch.cuda.synchronize()
+    po, mo, vo = oadam.step(p, g, m, v, t, 1e-3)
+    _within_ulp(dev[0].cpu().numpy(), po, 1, "param")
+    _within_ulp(dev[2].cpu().numpy(), mo, 1, "m")
+    _within_ulp(dev[3].cpu().numpy(), vo, 1, "v")
