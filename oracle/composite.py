@@ -101,15 +101,21 @@ def composite_tile(ids, px, py, mean2d, conic, opac, rgb, cfg, want_pairs=False)
 
     Returns dict with C [P,3], T [P], last [P] (1 + position in ``ids`` of the
     last contributing splat, 0 if none), flag [P] (some skip/stop decision of
-    that pixel lies within a relative margin FLAG_REL of its threshold) and,
-    if ``want_pairs``, the per-pair arrays of contributing pairs for the
-    reverse pass.
+    that pixel lies within a relative margin FLAG_REL of its threshold),
+    jump [P] (a bound on how far the pixel's colour can move if those
+    decisions went the other way, in units of max|colour - background|: the
+    transmittance-weighted alpha alpha T of every splat whose skip or stop
+    decision is flagged, plus t_min for a flagged stop, after which the rest
+    of the list adds less than t_min; the alpha clamp is continuous and adds
+    nothing) and, if ``want_pairs``, the per-pair arrays of contributing pairs
+    for the reverse pass.
     """
     P = len(px)
     C = np.zeros((P, 3))
     T = np.ones(P)
     last = np.zeros(P, np.int64)
     flag = np.zeros(P, bool)
+    jump = np.zeros(P)
     done = np.zeros(P, bool)
     amin, amax, tmin = cfg.alpha_min, cfg.alpha_max, cfg.t_min
     pairs = []
@@ -133,14 +139,21 @@ def composite_tile(ids, px, py, mean2d, conic, opac, rgb, cfg, want_pairs=False)
         upto = (kk <= s_idx[:, None]) & ~done[:, None]
         m = upto & (raw > 0.0)
         if amin > 0:
-            flag |= (m & (np.abs(alpha - amin) < FLAG_REL * amin)).any(axis=1)
+            fa = m & (np.abs(alpha - amin) < FLAG_REL * amin)
+            flag |= fa.any(axis=1)
+            jump += np.sum(np.where(fa, alpha * Texcl, 0.0), axis=1)
         flag |= (m & (np.abs(raw - amax) < FLAG_REL * amax)).any(axis=1)
         if tmin > 0:
-            flag |= (upto & valid & (np.abs(Tincl - tmin) < FLAG_REL * tmin)).any(axis=1)
+            ft = upto & valid & (np.abs(Tincl - tmin) < FLAG_REL * tmin)
+            flag |= ft.any(axis=1)
+            jump += np.sum(np.where(ft, alpha * Texcl + tmin, 0.0), axis=1)
         if cfg.kernel == "gaussian":
             # the 3-sigma cut is a jump of alpha (o * e^-4.5)
             e2 = extent(cfg) ** 2
-            flag |= (upto & (np.abs(D * D - e2) < FLAG_REL * e2)).any(axis=1)
+            fg = upto & (np.abs(D * D - e2) < FLAG_REL * e2)
+            flag |= fg.any(axis=1)
+            a_cut = opac[sl][None, :] * kernel_value(e2 * (1.0 - FLAG_REL), cfg)[1]
+            jump += np.sum(np.where(fg, np.minimum(amax, a_cut) * Texcl, 0.0), axis=1)
         any_c = contrib.any(axis=1)
         last_local = np.where(any_c, len(sl) - np.argmax(contrib[:, ::-1], axis=1), 0)
         last = np.where(any_c, k0 + last_local, last)
@@ -153,7 +166,7 @@ def composite_tile(ids, px, py, mean2d, conic, opac, rgb, cfg, want_pairs=False)
                               D=D[pp, kk2], L=L[pp, kk2], raw=raw[pp, kk2],
                               alpha=alpha[pp, kk2], Tb=Texcl[pp, kk2]))
         done |= has_stop
-    out = dict(C=C, T=T, last=last, flag=flag)
+    out = dict(C=C, T=T, last=last, flag=flag, jump=jump)
     if want_pairs:
         if pairs:
             out["pairs"] = {k: np.concatenate([d[k] for d in pairs]) for k in pairs[0]}

@@ -58,6 +58,7 @@ class Forward:
     final_T: np.ndarray = None                    # [P]
     last: np.ndarray = None                       # [P]
     flag: np.ndarray = None                       # [P]
+    jump: np.ndarray = None                       # [P] colour-jump bound of flagged pixels
     tiles_done: np.ndarray = None                 # [T] bool: composited
     tile_res: dict = field(default_factory=dict)  # gtile -> composite result (pairs)
 
@@ -107,6 +108,7 @@ def render_forward(scene, scene_off, cams, cfg, tiles=None, want_pairs=False):
     fw.final_T = np.full(P, np.nan)
     fw.last = np.full(P, -1, np.int64)
     fw.flag = np.zeros(P, bool)
+    fw.jump = np.zeros(P)
     T_total = int(lay.tile_off[-1])
     fw.tiles_done = np.zeros(T_total, bool)
     tiles = range(T_total) if tiles is None else tiles
@@ -131,6 +133,7 @@ def render_forward(scene, scene_off, cams, cfg, tiles=None, want_pairs=False):
         fw.final_T[pix] = res["T"]
         fw.last[pix] = res["last"]
         fw.flag[pix] = res["flag"]
+        fw.jump[pix] = res["jump"]
         fw.tiles_done[gt] = True
         if want_pairs:
             res["pix"] = pix

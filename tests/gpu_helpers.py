@@ -189,22 +189,39 @@ def compare_projection(g, fw):
     np.testing.assert_allclose(g["rgb"][vis], rgb[vis], rtol=1e-6, atol=1e-7)
 
 
+# Flagged pixels (a skip/stop decision within 1e-4 relative of its threshold)
+# in the oracle's seeded cases: 0 on workload 1 and 8.5e-4 on sampled tiles
+# of workload 2, where each pixel tests hundreds of splats against the
+# alpha floor.  The fraction is bounded at 10x that rate.
+MAX_FLAGGED_FRAC = 1e-2
+
+
 def compare_forward(g, fw, cams, tiles_mask_pix=None):
     flag = fw.flag.copy()
     done = ~np.isnan(fw.final_T)
     if tiles_mask_pix is not None:
         done &= tiles_mask_pix
     ok = done & ~flag
-    say(f"  pixels compared: {ok.sum()} (flagged near a threshold: {(done & flag).sum()})")
+    fl = done & flag
+    frac = fl.sum() / max(1, done.sum())
+    say(f"  pixels compared: {ok.sum()} (flagged near a threshold: {fl.sum()}, "
+        f"fraction {frac:.2e})")
+    assert frac <= MAX_FLAGGED_FRAC or fl.sum() <= 2, f"flagged fraction {frac:.3e}"
     img_ok = pixel_flags_to_image(ok, cams)
     assert_close("image", g["image"], fw.image, mask=img_ok)
     assert_close("final_T", g["final_T"], fw.final_T, mask=ok)
     np.testing.assert_array_equal(g["last"][ok], fw.last[ok])
-    # flagged pixels: a decision near a threshold may flip; bound the jump
-    fl = done & flag
+    # flagged pixels: a decision near a threshold may flip; the colour moves
+    # by at most the oracle's jump bound times max|colour - background|
     if fl.any():
         imf = pixel_flags_to_image(fl, cams)
-        assert np.max(np.abs(g["image"][imf] - fw.image[imf])) < 0.05
+        rgb = np.concatenate([p["rgb"] for p in fw.proj])
+        scale = float(np.max(np.abs(rgb))) + float(np.max(np.abs(fw.cfg.bg)))
+        bound = pixel_flags_to_image(fw.jump, cams)[imf] * scale * (1 + 1e-3) + 1e-6 * scale
+        dev = np.abs(g["image"][imf] - fw.image[imf])
+        say(f"  flagged pixels: largest colour change {dev.max():.2e}, "
+            f"largest bound {bound.max():.2e}")
+        assert np.all(dev <= bound), f"flagged pixel moved {dev.max():.3e} beyond its bound"
     return ok
 
 

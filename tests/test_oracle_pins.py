@@ -265,6 +265,38 @@ def test_early_stop_closed_form(stop_after):
     assert fw.last[pix] == stop_after
 
 
+def test_flagged_pixels_move_within_their_jump_bound():
+    """A flagged pixel's decision may go the other way on another machine; the
+    oracle's per-pixel jump bound must cover that.  Moving the alpha floor
+    and the stop threshold by 0.99 of the flag margin either way flips the
+    flagged decisions of sampled tiles of workload 2 (100k splats, 720p); every
+    pixel's colour must then stay within jump * max|colour - background| of
+    the unperturbed composite, and unflagged pixels must not move at all."""
+    from oracle.composite import FLAG_REL
+    sc, off, cams = scenes.workload(2)
+    rng = np.random.default_rng(0)
+    tiles = rng.choice(80 * 45, 60, replace=False)
+    base_cfg = RasterConfig()
+    fw = render_forward(sc, off, cams, base_cfg, tiles=tiles)
+    done = ~np.isnan(fw.final_T)
+    assert 0 < fw.flag[done].sum() < 0.01 * done.sum()
+    rgb = np.concatenate([p["rgb"] for p in fw.proj])
+    scale = float(np.max(np.abs(rgb)))
+    img_done = np.concatenate([done] * 3)
+    flag3 = np.concatenate([fw.flag] * 3)
+    bound3 = np.concatenate([fw.jump] * 3) * scale
+    moved = 0
+    for fa, ft in [(1 - 0.99 * FLAG_REL, 1.0), (1 + 0.99 * FLAG_REL, 1.0),
+                   (1.0, 1 - 0.99 * FLAG_REL), (1.0, 1 + 0.99 * FLAG_REL)]:
+        cfg = RasterConfig(alpha_min=base_cfg.alpha_min * fa, t_min=base_cfg.t_min * ft)
+        fp = render_forward(sc, off, cams, cfg, tiles=tiles)
+        d = np.abs(fp.image - fw.image)
+        assert np.all(d[img_done & ~flag3] == 0.0)
+        assert np.all(d[img_done & flag3] <= bound3[img_done & flag3] * (1 + 1e-9) + 1e-15)
+        moved += int(np.count_nonzero(d[img_done & flag3]))
+    assert moved > 0       # the perturbations did flip decisions
+
+
 def test_transmittance_telescopes_and_bounds():
     sc, off, cams = scenes.workload(1)
     cfg = RasterConfig()
@@ -336,6 +368,36 @@ def test_sort_and_ranges_against_python():
         keys = [(int(fw.depth_key[i]), i) for i in lst]
         assert keys == sorted(keys)
     assert fw.ranges[-1] == len(fw.sorted_ids) == int(fw.ntiles.sum())
+
+
+@pytest.mark.parametrize("case", ["workload1", "three_scenes_six_cameras"])
+def test_tile_list_equals_the_sorted_lists(case):
+    """binning.tile_list (one tile's list from its plain definition, the
+    reference list of every sampled tile in the full-size GPU tests) equals
+    the tile's range of the globally sorted intersections (pinned to Python's
+    sorted() above), for every tile: one camera, and three scenes seen by six
+    cameras of uneven, ragged sizes (camera lookup, tile offsets, pair
+    offsets).  The tile shapes include a non-square one, so swapped tile
+    coordinates cannot pass."""
+    if case == "workload1":
+        sc, off, cams = scenes.workload(1)
+        cfgs = [RasterConfig()]
+    else:
+        scs = [scenes.make_scene(n, 900 + i, -3.0, 0.5, 0) for i, n in enumerate((300, 500, 200))]
+        sc, off = scenes.concat_scenes(scs)
+        res = [(96, 64), (130, 70), (64, 64), (200, 90), (50, 120), (128, 96)]
+        cams = scenes.sphere_cameras(6, 4.0, res, scene_of_cam=[0, 1, 2, 0, 1, 2])
+        cfgs = [RasterConfig(), RasterConfig(tile_w=32, tile_h=8)]
+    for cfg in cfgs:
+        fw = render_forward(sc, off, cams, cfg, tiles=[])
+        T = int(fw.lay.tile_off[-1])
+        nonempty = 0
+        for t in range(T):
+            want = fw.sorted_ids[fw.ranges[t]:fw.ranges[t + 1]]
+            got = binning.tile_list(fw.rect, fw.ntiles, fw.depth_key, t, fw.lay)
+            np.testing.assert_array_equal(got, want, err_msg=f"tile {t}")
+            nonempty += len(want) > 0
+        assert nonempty > T // 2
 
 
 def test_binning_fp32_tracks_fp64():
@@ -603,13 +665,17 @@ def test_mean2d_norm_is_the_norm_of_the_projected_centre_gradient():
     assert np.count_nonzero(g["mean2d_norm"]) >= 3
 
 
-@pytest.mark.parametrize("ags", [False, True])
+@pytest.mark.parametrize("ags,ags_arg,ags_scope",
+                         [(False, 0, 0), (True, 0, 0), (True, 1, 0), (True, 0, 1), (True, 1, 1)])
 @pytest.mark.parametrize("deg", [0, 3])
-def test_reverse_pass_against_autograd(ags, deg):
+def test_reverse_pass_against_autograd(ags, ags_arg, ags_scope, deg):
+    """The oracle's reverse pass against autograd of an independent untiled
+    transcription (tests/torch_reference.py), AGS off and under each reading
+    of its weight's argument and scope (Eq. 13-14)."""
     torch = pytest.importorskip("torch")
     from tests import torch_reference as tr
     sc, cams, G = _tiny_grad_problem(5 + deg, deg=deg, n=15)
-    cfg = RasterConfig.strict(ags=ags)
+    cfg = RasterConfig.strict(ags=ags, ags_arg=ags_arg, ags_scope=ags_scope)
     _, g = _loss_and_grads(sc, cams, G, cfg)
     W, H = int(cams.width[0]), int(cams.height[0])
     fw = render_forward(sc, np.array([0, sc.n]), cams, cfg, tiles=[])
@@ -620,32 +686,42 @@ def test_reverse_pass_against_autograd(ags, deg):
     img = tr.render(*ps[:4], ps[4], deg, torch.tensor(cams.viewmat[0].astype(np.float64)),
                     [float(v) for v in cams.intrin[0].astype(np.float64)], W, H, order,
                     lam=cfg.lambda_, eps=cfg.eps2d, clip=cfg.clip, alpha_max=cfg.alpha_max,
-                    ags=ags)
+                    ags=ags, ags_arg=ags_arg, ags_scope=ags_scope)
     loss = (img.reshape(-1) * torch.tensor(G.astype(np.float64))).sum()
     loss.backward()
     for name, p in zip(("means", "scales", "quats", "opacity", "sh"), ps):
         assert _rms_close(g[name], p.grad.numpy(), 1e-8), name
 
 
-def test_ags_single_splat_closed_form():
-    """d C / d mean2d = rgb o (x - mu') / (lambda sigma r), times exp(-(r/sigma)^2)
-    under AGS with the raw distance."""
-    for ags in (False, True):
-        sc, cams, cfg, sigma = _iso_setup(s=0.3, o=0.8, W=32, H=32, strict=True, ags=ags)
-        W = H = 32
-        G = np.zeros(3 * W * H, np.float32)
-        px, py = 19, 13
-        G[0 * W * H + py * W + px] = 1.0        # red channel at one pixel
-        fw = render_forward(sc, np.array([0, 1]), cams, cfg, want_pairs=True)
-        g = render_backward(fw, sc, cams, G)
-        dx, dy = px + 0.5 - W / 2, py + 0.5 - H / 2
-        r = math.hypot(dx, dy)
-        o = float(np.float32(0.8))
-        fac = 0.5 * o / (cfg.lambda_ * sigma * r)
-        if ags:
-            fac *= math.exp(-(r / sigma) ** 2)
-        np.testing.assert_allclose(g["pair"]["mean2d"][0], [fac * dx, fac * dy], rtol=1e-10)
-        # colour and opacity gradients are not scaled (scope 0)
-        L = 1 - r / (cfg.lambda_ * sigma)
-        np.testing.assert_allclose(g["pair"]["opacity"][0], 0.5 * L, rtol=1e-10)
-        np.testing.assert_allclose(g["pair"]["rgb"][0], [o * L, 0, 0], rtol=1e-10)
+@pytest.mark.parametrize("ags,ags_arg,ags_scope",
+                         [(False, 0, 0), (True, 0, 0), (True, 1, 0), (True, 0, 1), (True, 1, 1)])
+def test_ags_single_splat_closed_form(ags, ags_arg, ags_scope):
+    """One isotropic splat, D' = r / sigma (Eq. 11 with Sigma_2D = sigma^2 I):
+    d C / d mean2d = rgb o (x - mu') / (lambda sigma r); AGS (Eq. 13-14)
+    multiplies it by omega = exp(-D'^2) (raw distance, ags_arg 0) or
+    exp(-(D'/lambda)^2) (ags_arg 1).  Scope 0 leaves the colour and opacity
+    gradients unscaled (dC/do = rgb L', dC/drgb = o L'); scope 1 multiplies
+    them by the same omega."""
+    sc, cams, cfg, sigma = _iso_setup(s=0.3, o=0.8, W=32, H=32, strict=True, ags=ags,
+                                      ags_arg=ags_arg, ags_scope=ags_scope)
+    W = H = 32
+    G = np.zeros(3 * W * H, np.float32)
+    px, py = 19, 13
+    G[0 * W * H + py * W + px] = 1.0        # red channel at one pixel
+    fw = render_forward(sc, np.array([0, 1]), cams, cfg, want_pairs=True)
+    g = render_backward(fw, sc, cams, G)
+    dx, dy = px + 0.5 - W / 2, py + 0.5 - H / 2
+    r = math.hypot(dx, dy)
+    Dp = r / sigma
+    o = float(np.float32(0.8))
+    omega = 1.0
+    if ags:
+        omega = math.exp(-Dp * Dp) if ags_arg == 0 else math.exp(-(Dp / cfg.lambda_) ** 2)
+    # the two readings of the weight differ by orders of magnitude here
+    assert 0.02 < Dp / cfg.lambda_ < 0.9
+    fac = 0.5 * o / (cfg.lambda_ * sigma * r) * omega
+    np.testing.assert_allclose(g["pair"]["mean2d"][0], [fac * dx, fac * dy], rtol=1e-10)
+    L = 1 - r / (cfg.lambda_ * sigma)
+    sc_w = omega if ags_scope == 1 else 1.0
+    np.testing.assert_allclose(g["pair"]["opacity"][0], 0.5 * L * sc_w, rtol=1e-10)
+    np.testing.assert_allclose(g["pair"]["rgb"][0], [o * L * sc_w, 0, 0], rtol=1e-10)

@@ -35,9 +35,15 @@ def sh_basis(d, degree):
 
 
 def render(means, scales, quats, opac, sh, degree, viewmat, intrin, W, H, order,
-           lam=2.5, eps=0.3, clip=1.3, alpha_max=0.99, ags=False, ags_arg=0):
+           lam=2.5, eps=0.3, clip=1.3, alpha_max=0.99, ags=False, ags_arg=0, ags_scope=0):
     """Image [3, H, W] for one camera.  ``order`` lists the visible splats in
-    depth order."""
+    depth order.
+
+    Adaptive gradient scaling (ags) leaves the value unchanged and multiplies
+    gradients by omega per (pixel, splat) pair, written as
+    v.detach() + omega (v - v.detach()): with ags_scope 0 on the kernel value
+    L' (the geometric path only), with ags_scope 1 on alpha and on the pair's
+    colour weight (every gradient of the pair)."""
     q = quats / quats.norm(dim=1, keepdim=True)
     w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
     R = torch.stack([
@@ -82,13 +88,21 @@ def render(means, scales, quats, opac, sh, degree, viewmat, intrin, W, H, order,
     qf = A[o] * dx * dx + 2 * B[o] * dx * dy + Cc[o] * dy * dy
     D = torch.sqrt(torch.clamp(qf, min=1e-300))
     L = torch.clamp(1 - D / lam, min=0.0)
+    om = None
     if ags:
         arg = D if ags_arg == 0 else D / lam
         om = torch.exp(-arg * arg).detach()
-        L = L.detach() + om * (L - L.detach())
+        if ags_scope == 0:
+            L = L.detach() + om * (L - L.detach())
     alpha = torch.clamp(opac[o][None, :] * L, max=alpha_max)
+    if ags and ags_scope == 1:
+        alpha = alpha.detach() + om * (alpha - alpha.detach())
     one = 1 - alpha
     Tb = torch.cat([torch.ones_like(one[:, :1]), torch.cumprod(one, dim=1)[:, :-1]], dim=1)
     wgt = alpha * Tb
-    img = wgt @ rgb[o]
+    col = rgb[o]
+    if ags and ags_scope == 1:
+        img = wgt @ col.detach() + (wgt.detach() * om) @ (col - col.detach())
+    else:
+        img = wgt @ col
     return img.T.reshape(3, H, W)
