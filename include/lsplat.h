@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LSPLAT_VERSION 170
+#define LSPLAT_VERSION 171
 
 typedef enum {
   LS_OK = 0,
@@ -354,6 +354,31 @@ ls_status ls_rasterize_bwd(const ls_config* cfg, const ls_splats* splats,
 ls_status ls_loss_workspace_size(const ls_cameras* cams, size_t* bytes);
 ls_status ls_loss(const ls_cameras* cams, const float* image, const float* target,
                   float* dL_dimage, double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ls_loss without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture that must not call hipMalloc,
+ * tight serving loops, harnesses that forbid allocation.  Same arguments
+ * (minus ws and ws_bytes), checks, kernels and results as ls_loss; it calls no
+ * hipMalloc, hipFree or other allocating routine (with kernel timing enabled
+ * it is not timed, since timing creates events).
+ * Scratch: the derivative maps and sums live in a static device array of
+ * LS_LOSS_NOALLOC_SCRATCH_BYTES (144 MiB) that each GPU the library runs on
+ * holds until the process ends.  A call needs ls_loss_workspace_size() bytes
+ * of it (72 bytes per pixel plus 24 per camera, each rounded up to 256): at
+ * most 2,097,148 pixels for one camera, e.g. one 1920 x 1080 view.  Larger
+ * inputs return LS_ERR_INVALID_ARG before anything is launched.
+ * The array's address on the stream's device is looked up on the first call
+ * there (that call is not legal inside a stream capture on a device the
+ * library has not used yet: make one call outside the capture first).
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (each call clears the sums it needs): calls that overlap on one
+ * GPU (concurrent streams, threads or processes' graphs) race and give wrong
+ * results.  Order them on one stream.
+ */
+#define LS_LOSS_NOALLOC_SCRATCH_BYTES ((size_t)144 << 20)
+ls_status ls_loss_noalloc(const ls_cameras* cams, const float* image, const float* target,
+                          float* dL_dimage, double* loss, void* stream);
 
 /*
  * Adam (Kingma and Ba 2015), the optimiser of the 3DGS training the paper

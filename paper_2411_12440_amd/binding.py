@@ -109,6 +109,8 @@ def _load() -> C.CDLL:
         "ls_loss_workspace_size": ([P(Cams), P(C.c_size_t)], C.c_int),
         "ls_loss": ([P(Cams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
+        "ls_loss_noalloc": ([P(Cams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                            C.c_int),
         "ls_adam": ([P(AdamParams), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p], C.c_int),
         "ls_adam_device_step": ([P(AdamParams), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
@@ -130,7 +132,7 @@ def _load() -> C.CDLL:
 LIB = _load()
 EXPORTS = ("ls_version", "ls_last_error", "ls_workspace_size", "ls_workspace_layout",
            "ls_project", "ls_bin_sort", "ls_rasterize_fwd", "ls_rasterize_bwd",
-           "ls_loss_workspace_size", "ls_loss", "ls_adam", "ls_adam_device_step", "ls_densify_stats",
+           "ls_loss_workspace_size", "ls_loss", "ls_loss_noalloc", "ls_adam", "ls_adam_device_step", "ls_densify_stats",
            "ls_densify_select", "ls_profile_enable", "ls_profile_read")
 
 
@@ -237,6 +239,15 @@ def ls_loss_workspace_size(cams: CamerasHost) -> int:
 def ls_loss(cams: CamerasHost, image, target, dL_dimage, loss, ws, stream=None):
     _check(LIB.ls_loss(C.byref(cams.c), _ptr(image), _ptr(target), _ptr(dL_dimage), _ptr(loss),
                        _ptr(ws), ws.numel(), _stream(stream)))
+
+
+# bytes of the static scratch behind ls_loss_noalloc (LS_LOSS_NOALLOC_SCRATCH_BYTES)
+LOSS_NOALLOC_SCRATCH_BYTES = 144 << 20
+
+
+def ls_loss_noalloc(cams: CamerasHost, image, target, dL_dimage, loss, stream=None):
+    _check(LIB.ls_loss_noalloc(C.byref(cams.c), _ptr(image), _ptr(target), _ptr(dL_dimage),
+                               _ptr(loss), _stream(stream)))
 
 
 def adam_params(lr, step, beta1=0.9, beta2=0.999, eps=1e-15) -> AdamParams:

@@ -353,6 +353,29 @@ ls_status ls_loss(const ls_cameras* cams, const float* image, const float* targe
   return LS_OK;
 }
 
+ls_status ls_loss_noalloc(const ls_cameras* cams, const float* image, const float* target,
+                          float* dL_dimage, double* loss, void* stream) {
+  int64_t P = 0;
+  ls_status st = check_loss_cams(cams, &P);
+  if (st != LS_OK) return st;
+  if (!image || !target || !dL_dimage || !loss)
+    return fail(LS_ERR_INVALID_ARG, "image/target/dL_dimage/loss is NULL");
+  const size_t need = loss_workspace_bytes(P, cams->n_cams);
+  if (need > LS_LOSS_NOALLOC_SCRATCH_BYTES)
+    return fail(LS_ERR_INVALID_ARG,
+                "ls_loss_noalloc: %lld pixels over %d cameras need %zu bytes of scratch; the static "
+                "scratch holds %zu (about %zu pixels); use ls_loss with a workspace",
+                (long long)P, cams->n_cams, need, (size_t)LS_LOSS_NOALLOC_SCRATCH_BYTES,
+                (size_t)LS_LOSS_NOALLOC_SCRATCH_BYTES / 72);
+  char* ws = nullptr;
+  hipError_t e = loss_noalloc_scratch((hipStream_t)stream, &ws);
+  if (e != hipSuccess) return hip_fail(e, "loss scratch address");
+  e = launch_loss(cams->h_width, cams->h_height, cams->n_cams, image, target, dL_dimage, loss, ws,
+                  (hipStream_t)stream, false);
+  if (e != hipSuccess) return hip_fail(e, "loss");
+  return LS_OK;
+}
+
 static ls_status check_adam(const ls_adam_params* prm, bool need_step, int64_t n, float* param,
                             const float* grad, float* m, float* v) {
   if (!prm) return fail(LS_ERR_INVALID_ARG, "prm is NULL");

@@ -269,7 +269,9 @@ const uint32_t* det_slots(const Plan& p, char* ws);
 size_t loss_workspace_bytes(int64_t P, int C);
 hipError_t launch_loss(const int32_t* W, const int32_t* H, int C, const float* image,
                        const float* target, float* dL_dimage, double* loss, char* ws,
-                       hipStream_t s);
+                       hipStream_t s, bool timed = true);
+// device address of the static loss scratch on the stream's device
+hipError_t loss_noalloc_scratch(hipStream_t s, char** out);
 hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splats* sp, char* ws,
                              const float* final_T, const int32_t* last, const float* dL_dimage,
                              const float* dL_dalpha, const ls_grads* g, hipStream_t s);

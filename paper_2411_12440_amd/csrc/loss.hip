@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
@@ -285,6 +286,47 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of ls_loss_noalloc: the derivative maps and per-camera sums
+// of one call, for callers that cannot allocate.  Every device the library
+// runs on holds its own copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, never a device address: the address on each
+// device comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LS_LOSS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxScratchDevices];   // per device ordinal, set on first use
+}  // namespace
+
+hipError_t loss_noalloc_scratch(hipStream_t s, char** out) {
+  *out = nullptr;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  int dev = cur;
+  if (s != nullptr && (e = hipStreamGetDevice(s, &dev)) != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    // the stream's device must be current while its copy's address is taken
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 size_t loss_workspace_bytes(int64_t P, int C) {
   // FP64 derivative maps (3 per channel and pixel), then the per-camera sums
   return align256((size_t)P * 72) + align256((size_t)C * 24);
@@ -292,13 +334,13 @@ size_t loss_workspace_bytes(int64_t P, int C) {
 
 hipError_t launch_loss(const int32_t* W, const int32_t* H, int C, const float* image,
                        const float* target, float* dL_dimage, double* loss, char* ws,
-                       hipStream_t s) {
+                       hipStream_t s, bool timed) {
   int64_t P = 0;
   for (int c = 0; c < C; ++c) P += (int64_t)W[c] * H[c];
   double* coef = (double*)ws;
   double* acc = (double*)(ws + align256((size_t)P * 72));
   hipError_t e;
-  ProfScope ps("loss", s);
+  ProfScope ps(timed ? "loss" : nullptr, s);
   hipLaunchKernelGGL(loss_zero_kernel, dim3((3 * C + 255) / 256), dim3(256), 0, s, acc, 3 * C);
   if ((e = hipGetLastError())) return e;
   double win[kWin], wsum = 0.0;

@@ -44,7 +44,7 @@ Profiler& prof() {
 
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s), slot_(-1) {
   Profiler& p = prof();
-  if (!p.enabled) return;
+  if (!p.enabled || !name) return;   // a null name: untimed (creates no events)
   hipEvent_t a = p.get(), b = p.get();
   if (!a || !b) return;
   if (hipEventRecord(a, s) != hipSuccess) return;

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(B.EXPORTS) == set(declared_functions())
-    assert B.ls_version() == 170
+    assert B.ls_version() == 171
 
 
 def _cams(w=(128,), h=(128,), scene=(0,), off=(0, 10)):
@@ -158,6 +158,13 @@ def test_loss_arguments_checked():
     assert lib.ls_loss(C.byref(cams.c), one, one, one, one, base + 8, n, None) == -5
     assert lib.ls_loss(C.byref(cams.c), one, one, one, one, base, n - 1, None) == -5
     assert b"loss needs" in lib.ls_last_error()
+    # the entry point without a workspace: same checks, and inputs beyond its
+    # static scratch are refused before anything touches a device
+    assert lib.ls_loss_noalloc(C.byref(cams.c), None, one, one, one, None) == -1
+    big = _cams(w=(1920, 1024), h=(1080, 64), scene=(0, 0))
+    assert B.ls_loss_workspace_size(big) > B.LOSS_NOALLOC_SCRATCH_BYTES
+    assert lib.ls_loss_noalloc(C.byref(big.c), one, one, one, one, None) == -1
+    assert b"static scratch" in lib.ls_last_error()
 
 
 def test_training_stage_arguments_checked():
