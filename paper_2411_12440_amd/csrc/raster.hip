@@ -330,7 +330,9 @@ void raster_fwd_kernel(
     for (int i = tid; i < kExpTabN; i += NTB) s_exptab[i] = exp_neg((double)i / kExpTabStep);
   const int64_t* ranges = ranges_all + (int64_t)c * (T_all + 1);
   const int32_t len = (int32_t)(ranges[tile + 1] - ranges[tile]);
-  if (c > 0 && len == 0) return;
+  // a live tile with no entries in this chunk keeps its state; in the last
+  // chunk it still writes the outputs of the pixels that never stopped
+  if (c > 0 && c < K - 1 && len == 0) return;
   const int64_t start = chunk_base[c] + ranges[tile];
   int32_t prefix = 0;
   for (int cc = 0; cc < c; ++cc) {
@@ -348,9 +350,12 @@ void raster_fwd_kernel(
 
   // per pixel of this lane: transmittance and colour (FP64), the stop flag
   // and `last`, continued from the previous chunks
+  // A pixel's outputs are written once, in the chunk where it stops (or the
+  // last chunk); a pixel that stopped in an earlier chunk is not touched
+  // again (`fin`), and only a live pixel's state is carried to the next chunk.
   double ly[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
   int64_t pix[PPL];
-  bool inside[PPL], done[PPL];
+  bool inside[PPL], done[PPL], fin[PPL];
   int32_t lastc[PPL];
   uint32_t ncon = 0;
 #pragma unroll
@@ -364,14 +369,17 @@ void raster_fwd_kernel(
     cr[j] = cg[j] = cb[j] = 0.0;
     lastc[j] = 0;
     done[j] = !inside[j];
+    fin[j] = !inside[j];
     if (c > 0 && inside[j]) {
-      const double4 sv = state[pix[j]];
-      T[j] = sv.x;
-      cr[j] = sv.y;
-      cg[j] = sv.z;
-      cb[j] = sv.w;
-      done[j] = done_px[pix[j]] != 0;
-      lastc[j] = last[pix[j]];
+      fin[j] = done[j] = done_px[pix[j]] != 0;
+      if (!done[j]) {
+        const double4 sv = state[pix[j]];
+        T[j] = sv.x;
+        cr[j] = sv.y;
+        cg[j] = sv.z;
+        cb[j] = sv.w;
+        lastc[j] = last[pix[j]];
+      }
     }
   }
   auto all_done = [&]() {
@@ -415,10 +423,20 @@ void raster_fwd_kernel(
     }
   }
   const int64_t plane = (int64_t)ci.W * ci.H;
+  const bool more = K > 1 && c < K - 1;   // chunks follow this one
   bool live = false;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    if (!inside[j]) continue;
+    if (fin[j]) continue;
+    if (more && !done[j]) {
+      // still compositing: carry the state (done_px is already 0 after the
+      // first chunk)
+      state[pix[j]] = make_double4(T[j], cr[j], cg[j], cb[j]);
+      last[pix[j]] = lastc[j];
+      if (c == 0) done_px[pix[j]] = 0;
+      live = true;
+      continue;
+    }
     const int64_t ib = 3 * ci.pix_off + (pix[j] - ci.pix_off);
     image[ib] = (float)(cr[j] + T[j] * (double)rp.bg0);
     image[ib + plane] = (float)(cg[j] + T[j] * (double)rp.bg1);
@@ -426,11 +444,7 @@ void raster_fwd_kernel(
     final_T[pix[j]] = (float)T[j];
     t64[pix[j]] = T[j];   // the backward pass starts from the FP64 value
     last[pix[j]] = lastc[j];
-    if (K > 1 && c < K - 1) {
-      state[pix[j]] = make_double4(T[j], cr[j], cg[j], cb[j]);
-      done_px[pix[j]] = done[j] ? 1 : 0;
-      live = live || !done[j];
-    }
+    if (more) done_px[pix[j]] = 1;
   }
   // contributing pairs of the tile (a statistic for throughput accounting)
   for (int d = 32; d > 0; d >>= 1) ncon += __shfl_xor(ncon, d, 64);
