@@ -145,6 +145,63 @@ def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+_DTYPES = {}
+
+
+def _dtype(name):
+    # torch is imported lazily so that the CPU-side ABI checks need no GPU
+    if not _DTYPES:
+        import torch
+        _DTYPES.update(f32=torch.float32, f64=torch.float64, i32=torch.int32, i64=torch.int64,
+                       u8=torch.uint8)
+    return _DTYPES[name]
+
+
+def _meta(t, what: str, dtype: str, numel=None, optional=False) -> bool:
+    """Check what the C side assumes of tensor ``t`` apart from its device:
+    the element type, a contiguous layout and the element count the entry
+    point will read or write.  Raises TypeError or ValueError instead of
+    handing the library a pointer it would misread.  False for an absent
+    optional tensor."""
+    if t is None:
+        if optional:
+            return False
+        raise ValueError(f"{what} is required")
+    if not hasattr(t, "data_ptr") or not hasattr(t, "dtype"):
+        raise TypeError(f"{what} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != _dtype(dtype):
+        raise TypeError(f"{what} must be {_dtype(dtype)}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if numel is not None and t.numel() != int(numel):
+        raise ValueError(f"{what} has {t.numel()} elements, expected {int(numel)}")
+    return True
+
+
+def _devs(*specs) -> list[int]:
+    """Pointers of several tensors, each spec (tensor, what, dtype[, numel[,
+    optional]]): every argument's type and size is checked before any
+    argument's device, so that a wrong argument is reported as such."""
+    present = [_meta(*sp) for sp in specs]
+    out = []
+    for sp, have in zip(specs, present):
+        t = sp[0]
+        if have and not t.is_cuda:
+            raise TypeError(f"{sp[1]} must be on a GPU (device {t.device})")
+        out.append(int(t.data_ptr()) if have else 0)
+    return out
+
+
+def _dev(t, what: str, dtype: str, numel=None, optional=False) -> int:
+    """Device pointer of one tensor after the checks of _meta and that its
+    memory is on a GPU."""
+    return _devs((t, what, dtype, numel, optional))[0]
+
+
+def _ws(t, what="workspace") -> int:
+    return _dev(t, what, "u8")
+
+
 def _stream(stream) -> int:
     return 0 if stream is None else int(stream)
 
@@ -160,9 +217,25 @@ class CamerasHost:
         self.h_height = np.ascontiguousarray(height, np.int32)
         self.h_scene = np.ascontiguousarray(scene_of_cam, np.int32)
         self.h_off = np.ascontiguousarray(scene_splat_off, np.int64)
-        self.c = Cams(len(self.h_width), len(self.h_off) - 1, _ptr(viewmat), _ptr(intrin),
+        n = len(self.h_width)
+        # device camera matrices are optional: the loss reads only the sizes
+        self.c = Cams(n, len(self.h_off) - 1,
+                      _dev(viewmat, "viewmat [C,3,4]", "f32", 12 * n, optional=True),
+                      _dev(intrin, "intrin [C,4]", "f32", 4 * n, optional=True),
                       self.h_width.ctypes.data, self.h_height.ctypes.data,
                       self.h_scene.ctypes.data, self.h_off.ctypes.data)
+
+    @property
+    def n_pixels(self) -> int:
+        return int(np.sum(self.h_width.astype(np.int64) * self.h_height.astype(np.int64)))
+
+    @property
+    def n_splats(self) -> int:
+        return int(self.h_off[-1]) if len(self.h_off) else 0
+
+    def require_matrices(self):
+        if self.viewmat is None or self.intrin is None:
+            raise ValueError("these cameras carry no device viewmat/intrin")
 
 
 def make_config(lambda_=2.5, eps2d=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
@@ -182,13 +255,48 @@ def make_config(lambda_=2.5, eps2d=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t
     return cfg
 
 
+def _sh_bands(sh, n: int, what: str) -> int:
+    K = sh.numel() // (3 * n) if n > 0 else 0
+    if n > 0 and (sh.numel() != 3 * n * K or K not in (1, 4, 9, 16)):
+        raise ValueError(f"{what} has {sh.numel()} elements, expected K*3*{n} with K in 1, 4, 9, 16")
+    return K
+
+
 def splats_struct(n, means, scales, quats, opacity, sh) -> Splats:
-    return Splats(n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh))
+    """Planar float32 device arrays: means/scales [3,n], quats [4,n],
+    opacity [n], sh [K,3,n]."""
+    ptrs = _devs((means, "means [3,n]", "f32", 3 * n), (scales, "scales [3,n]", "f32", 3 * n),
+                 (quats, "quats [4,n]", "f32", 4 * n), (opacity, "opacity [n]", "f32", n),
+                 (sh, "sh [K,3,n]", "f32"))
+    bands = _sh_bands(sh, n, "sh [K,3,n]")
+    st = Splats(n, *ptrs)
+    st.bands = bands
+    return st
 
 
 def grads_struct(means, scales, quats, opacity, sh, mean2d_norm=None) -> Grads:
-    return Grads(_ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh),
-                 _ptr(mean2d_norm))
+    """Gradient outputs; their sizes are checked against the splats and
+    cameras when ls_rasterize_bwd is called."""
+    g = Grads(*_devs((means, "grad means", "f32"), (scales, "grad scales", "f32"),
+                     (quats, "grad quats", "f32"), (opacity, "grad opacity", "f32"),
+                     (sh, "grad sh", "f32"), (mean2d_norm, "mean2d_norm", "f32", None, True)))
+    g.sizes = (means.numel(), scales.numel(), quats.numel(), opacity.numel(), sh.numel(),
+               None if mean2d_norm is None else mean2d_norm.numel())
+    return g
+
+
+def _check_splats(cfg: Config, splats: Splats, cams: CamerasHost):
+    if splats.n != cams.n_splats:
+        raise ValueError(f"splats.n = {splats.n}, the cameras' scenes hold {cams.n_splats}")
+    K = (cfg.sh_degree + 1) ** 2
+    if splats.n > 0 and getattr(splats, "bands", K) != K:
+        raise ValueError(f"sh holds {splats.bands} bands per channel, sh_degree "
+                         f"{cfg.sh_degree} needs {K}")
+
+
+def _n_pairs(cams: CamerasHost) -> int:
+    sizes = np.diff(cams.h_off)
+    return int(np.sum(sizes[cams.h_scene])) if len(cams.h_scene) else 0
 
 
 def ls_version() -> int:
@@ -208,26 +316,38 @@ def ls_workspace_layout(cfg: Config, cams: CamerasHost, capacity: int) -> Layout
 
 
 def ls_project(cfg, splats: Splats, cams: CamerasHost, ws, capacity, stream=None):
-    _check(LIB.ls_project(C.byref(cfg), C.byref(splats), C.byref(cams.c), _ptr(ws), ws.numel(),
+    cams.require_matrices()
+    _check_splats(cfg, splats, cams)
+    _check(LIB.ls_project(C.byref(cfg), C.byref(splats), C.byref(cams.c), _ws(ws), ws.numel(),
                           capacity, _stream(stream)))
 
 
 def ls_bin_sort(cfg, cams: CamerasHost, ws, capacity, stream=None):
-    _check(LIB.ls_bin_sort(C.byref(cfg), C.byref(cams.c), _ptr(ws), ws.numel(), capacity,
+    _check(LIB.ls_bin_sort(C.byref(cfg), C.byref(cams.c), _ws(ws), ws.numel(), capacity,
                            _stream(stream)))
 
 
 def ls_rasterize_fwd(cfg, cams: CamerasHost, ws, capacity, image, final_T, last, stream=None):
-    _check(LIB.ls_rasterize_fwd(C.byref(cfg), C.byref(cams.c), _ptr(ws), ws.numel(), capacity,
-                                _ptr(image), _ptr(final_T), _ptr(last), _stream(stream)))
+    P = cams.n_pixels
+    ptrs = _devs((ws, "workspace", "u8"), (image, "image", "f32", 3 * P),
+                 (final_T, "final_T", "f32", P), (last, "last", "i32", P))
+    _check(LIB.ls_rasterize_fwd(C.byref(cfg), C.byref(cams.c), ptrs[0], ws.numel(), capacity,
+                                *ptrs[1:], _stream(stream)))
 
 
 def ls_rasterize_bwd(cfg, splats: Splats, cams: CamerasHost, ws, capacity, final_T, last,
                      dL_dimage, dL_dalpha, grads: Grads, stream=None):
-    _check(LIB.ls_rasterize_bwd(C.byref(cfg), C.byref(splats), C.byref(cams.c), _ptr(ws),
-                                ws.numel(), capacity, _ptr(final_T), _ptr(last),
-                                _ptr(dL_dimage), _ptr(dL_dalpha), C.byref(grads),
-                                _stream(stream)))
+    P, n = cams.n_pixels, splats.n
+    _check_splats(cfg, splats, cams)
+    want = (3 * n, 3 * n, 4 * n, n, (cfg.sh_degree + 1) ** 2 * 3 * n, _n_pairs(cams))
+    names = ("grad means", "grad scales", "grad quats", "grad opacity", "grad sh", "mean2d_norm")
+    for name, have, need in zip(names, getattr(grads, "sizes", want), want):
+        if have is not None and have != need:
+            raise ValueError(f"{name} has {have} elements, expected {need}")
+    ptrs = _devs((ws, "workspace", "u8"), (final_T, "final_T", "f32", P), (last, "last", "i32", P),
+                 (dL_dimage, "dL_dimage", "f32", 3 * P), (dL_dalpha, "dL_dalpha", "f32", P, True))
+    _check(LIB.ls_rasterize_bwd(C.byref(cfg), C.byref(splats), C.byref(cams.c), ptrs[0],
+                                ws.numel(), capacity, *ptrs[1:], C.byref(grads), _stream(stream)))
 
 
 def ls_loss_workspace_size(cams: CamerasHost) -> int:
@@ -236,9 +356,16 @@ def ls_loss_workspace_size(cams: CamerasHost) -> int:
     return out.value
 
 
+def _loss_ptrs(cams: CamerasHost, image, target, dL_dimage, loss):
+    P3 = 3 * cams.n_pixels
+    return _devs((image, "image", "f32", P3), (target, "target", "f32", P3),
+                 (dL_dimage, "dL_dimage", "f32", P3), (loss, "loss", "f64", int(cams.c.n_cams)))
+
+
 def ls_loss(cams: CamerasHost, image, target, dL_dimage, loss, ws, stream=None):
-    _check(LIB.ls_loss(C.byref(cams.c), _ptr(image), _ptr(target), _ptr(dL_dimage), _ptr(loss),
-                       _ptr(ws), ws.numel(), _stream(stream)))
+    _meta(ws, "workspace", "u8")
+    _check(LIB.ls_loss(C.byref(cams.c), *_loss_ptrs(cams, image, target, dL_dimage, loss),
+                       _ws(ws), ws.numel(), _stream(stream)))
 
 
 # bytes of the static scratch behind ls_loss_noalloc (LS_LOSS_NOALLOC_SCRATCH_BYTES)
@@ -246,26 +373,40 @@ LOSS_NOALLOC_SCRATCH_BYTES = 144 << 20
 
 
 def ls_loss_noalloc(cams: CamerasHost, image, target, dL_dimage, loss, stream=None):
-    _check(LIB.ls_loss_noalloc(C.byref(cams.c), _ptr(image), _ptr(target), _ptr(dL_dimage),
-                               _ptr(loss), _stream(stream)))
+    _check(LIB.ls_loss_noalloc(C.byref(cams.c), *_loss_ptrs(cams, image, target, dL_dimage, loss),
+                               _stream(stream)))
 
 
 def adam_params(lr, step, beta1=0.9, beta2=0.999, eps=1e-15) -> AdamParams:
     return AdamParams(lr, beta1, beta2, eps, step)
 
 
+def _adam_ptrs(param, grad, m, v):
+    n = param.numel()
+    return n, _devs(*[(t, name, "f32", n) for t, name in
+                      ((param, "param"), (grad, "grad"), (m, "m"), (v, "v"))])
+
+
 def ls_adam(prm: AdamParams, param, grad, m, v, stream=None):
-    _check(LIB.ls_adam(C.byref(prm), param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
-                       _stream(stream)))
+    n, ptrs = _adam_ptrs(param, grad, m, v)
+    _check(LIB.ls_adam(C.byref(prm), n, *ptrs, _stream(stream)))
 
 
 def ls_adam_device_step(prm: AdamParams, step_dev, param, grad, m, v, stream=None):
-    _check(LIB.ls_adam_device_step(C.byref(prm), _ptr(step_dev), param.numel(), _ptr(param),
-                                   _ptr(grad), _ptr(m), _ptr(v), _stream(stream)))
+    _meta(step_dev, "step_dev", "i64", 1)
+    n, ptrs = _adam_ptrs(param, grad, m, v)
+    _check(LIB.ls_adam_device_step(C.byref(prm), _dev(step_dev, "step_dev", "i64", 1), n, *ptrs,
+                                   _stream(stream)))
 
 
 def densify_acc(grad, count, max_extent) -> DensifyAcc:
-    return DensifyAcc(_ptr(grad), _ptr(count), _ptr(max_extent))
+    """Per-splat accumulators: grad float32 [n], count int32 [n], max_extent
+    float32 [n]."""
+    n = grad.numel()
+    acc = DensifyAcc(*_devs((grad, "acc grad", "f32", n), (count, "acc count", "i32", n),
+                            (max_extent, "acc max_extent", "f32", n)))
+    acc.n = n
+    return acc
 
 
 # thresholds of the paper's densification table, in the order of the
@@ -279,15 +420,25 @@ def densify_params(scene_scale, thresholds=THRESH_3DLS, grow2d=False,
     return DensifyParams(*thresholds, scene_scale, int(grow2d), int(prune_big))
 
 
+def _check_acc(acc: DensifyAcc, n: int):
+    if getattr(acc, "n", n) != n:
+        raise ValueError(f"densification accumulators hold {acc.n} splats, expected {n}")
+
+
 def ls_densify_stats(cfg, cams: CamerasHost, ws, capacity, acc: DensifyAcc, stream=None):
-    _check(LIB.ls_densify_stats(C.byref(cfg), C.byref(cams.c), _ptr(ws), ws.numel(), capacity,
+    _check_acc(acc, cams.n_splats)
+    _check(LIB.ls_densify_stats(C.byref(cfg), C.byref(cams.c), _ws(ws), ws.numel(), capacity,
                                 C.byref(acc), _stream(stream)))
 
 
 def ls_densify_select(prm: DensifyParams, n, scales, opacity, acc: DensifyAcc, action,
                       counts=None, stream=None):
-    _check(LIB.ls_densify_select(C.byref(prm), n, _ptr(scales), _ptr(opacity), C.byref(acc),
-                                 _ptr(action), _ptr(counts), _stream(stream)))
+    opt = n == 0   # nothing is read or written for zero splats
+    if not opt:
+        _check_acc(acc, n)
+    sc, op, act, cnt = _devs((scales, "scales", "f32", 3 * n, opt), (opacity, "opacity", "f32", n, opt),
+                             (action, "action", "u8", n, opt), (counts, "counts", "i64", 3, True))
+    _check(LIB.ls_densify_select(C.byref(prm), n, sc, op, C.byref(acc), act, cnt, _stream(stream)))
 
 
 def ls_profile_enable(on: bool = True):

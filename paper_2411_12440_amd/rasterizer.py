@@ -46,10 +46,15 @@ class Rasterizer:
         self.ws = None
         self.layout = None
         self.image = self.final_T = self.last = None
+        # bumped by every call that overwrites what a backward pass reads (the
+        # projections, lists, final transmittance, `last`) and by a regrown
+        # workspace; RenderFunction checks it
+        self.generation = 0
         self._alloc(int(capacity) if capacity is not None else 1 << 20)
 
     # -- memory ---------------------------------------------------------------
     def _alloc(self, capacity: int):
+        self.generation += 1
         nbytes = B.ls_workspace_size(self.cfg, self.cams, capacity)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.capacity = capacity
@@ -91,13 +96,16 @@ class Rasterizer:
         return B.splats_struct(n, sp["means"], sp["scales"], sp["quats"], sp["opacity"], sp["sh"])
 
     def project(self, sp, stream=None):
+        self.generation += 1
         B.ls_project(self.cfg, self._splats(sp), self.cams, self.ws, self.capacity,
                      self._stream(stream))
 
     def bin_sort(self, stream=None):
+        self.generation += 1
         B.ls_bin_sort(self.cfg, self.cams, self.ws, self.capacity, self._stream(stream))
 
     def rasterize_fwd(self, stream=None):
+        self.generation += 1
         B.ls_rasterize_fwd(self.cfg, self.cams, self.ws, self.capacity, self.image,
                            self.final_T, self.last, self._stream(stream))
 
@@ -182,9 +190,26 @@ class StepGraph:
         self.graph.replay()
 
 
+class StaleForwardError(RuntimeError):
+    """The rasterizer ran another forward pass (or regrew its workspace)
+    after the one a backward pass belongs to."""
+
+
+def check_generation(rast, generation: int):
+    if rast.generation != generation:
+        raise StaleForwardError(
+            "the Rasterizer's workspace was overwritten by a later forward pass (generation "
+            f"{rast.generation}, this graph node's is {generation}); a Rasterizer holds the "
+            "state of one forward pass at a time: run backward before the next render through "
+            "it, or use one Rasterizer per live graph node")
+
+
 class RenderFunction(torch.autograd.Function):
     """image = render(means, scales, quats, opacity, sh) through a Rasterizer;
-    the backward pass is the library's hand-written reverse pass."""
+    the backward pass is the library's hand-written reverse pass.  The
+    Rasterizer's workspace holds one forward pass: a backward pass whose
+    forward was followed by another render through the same Rasterizer
+    raises StaleForwardError instead of returning wrong gradients."""
 
     @staticmethod
     def forward(ctx, means, scales, quats, opacity, sh, rast: Rasterizer):
@@ -193,10 +218,12 @@ class RenderFunction(torch.autograd.Function):
         image, _, _ = rast.forward(sp)
         ctx.rast = rast
         ctx.sp = sp
+        ctx.generation = rast.generation
         return image.clone()
 
     @staticmethod
     def backward(ctx, dL_dimage):
+        check_generation(ctx.rast, ctx.generation)
         g = ctx.rast.backward(ctx.sp, dL_dimage.contiguous())
         return g["means"], g["scales"], g["quats"], g["opacity"], g["sh"], None
 

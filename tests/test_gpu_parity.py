@@ -276,6 +276,29 @@ def test_autograd_function():
     compare_grads(got, go, scene)
 
 
+def test_autograd_stale_forward_raises():
+    """A second render through the same Rasterizer overwrites the workspace
+    the first graph node's backward pass reads: that backward raises, and the
+    second one (whose forward is current) still runs."""
+    import torch
+    from paper_2411_12440_amd.rasterizer import (Rasterizer, StaleForwardError, render,
+                                                 scene_to_device)
+    say("case: stale forward raises in backward")
+    scene = scenes.make_scene(300, 9, -3.0, 0.5, 0)
+    cams = scenes.front_camera(64, 48)
+    rast = Rasterizer(cams, np.array([0, scene.n]), sh_degree=0)
+    sp = scene_to_device(scene)
+    leaves1 = [sp[k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+    leaves2 = [sp[k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+    img1 = render(*leaves1, rast)
+    img2 = render(*leaves2, rast)
+    with pytest.raises(StaleForwardError):
+        img1.sum().backward()
+    img2.sum().backward()
+    torch.cuda.synchronize()
+    assert all(l.grad is not None and torch.isfinite(l.grad).all() for l in leaves2)
+
+
 @pytest.mark.parametrize("chunks", [1, 3])
 def test_deterministic_backward(chunks):
     """Deterministic mode: two backward passes give bitwise-equal splat
