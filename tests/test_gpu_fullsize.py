@@ -45,14 +45,21 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5, ags=True):
+def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5, ags=True,
+                    tile=(16, 16), batch=0, graph=False):
+    """graph=True: after the eager checks of the forward pass, the whole step
+    is captured in a StepGraph and replayed three times (eager work and a
+    synchronisation between replays); every replay's image, final_T and last
+    must equal the eager forward bit for bit, and the gradients of the last
+    replay are the ones checked against the oracle."""
     import torch
-    from paper_2411_12440_amd.rasterizer import Rasterizer, scene_to_device
+    from paper_2411_12440_amd.rasterizer import Rasterizer, StepGraph, scene_to_device
 
     scene, off, cams = scenes.workload(k)
     N = scene.n
     deg = scene.sh_degree
-    ocfg, gkw = cfg_pair(ags=ags, depth_chunks=7, kernel=kernel, lambda_=lambda_)
+    ocfg, gkw = cfg_pair(ags=ags, depth_chunks=7, kernel=kernel, lambda_=lambda_,
+                         tile_w=tile[0], tile_h=tile[1], batch=batch)
     sp = scene_to_device(scene)
     rast = Rasterizer(cams, off, capacity=1 << 24, sh_degree=deg, **gkw)
     rast.forward(sp)
@@ -159,7 +166,21 @@ def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5
     # of the FP32 per-pixel terms, which the chain through the projection can
     # amplify where the centre and conic terms of a large splat cancel, from
     # the projection backward itself.
-    grads = rast.backward(sp, torch.from_numpy(G).cuda())
+    if graph:
+        dimg = torch.from_numpy(G).cuda()
+        grads = {kk: torch.empty_like(v) for kk, v in sp.items()}
+        eager_out = [t.clone() for t in (rast.image, rast.final_T, rast.last)]
+        sg = StepGraph(rast, sp, dimg, grads)
+        for rep in range(3):
+            sg.replay()
+            junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+            torch.cuda.synchronize()
+            for a, b in zip((rast.image, rast.final_T, rast.last), eager_out):
+                assert torch.equal(a, b), f"replay {rep}: forward output differs from eager"
+            del junk
+        say("  three graph replays: forward outputs equal the eager pass bit for bit")
+    else:
+        grads = rast.backward(sp, torch.from_numpy(G).cuda())
     torch.cuda.synchronize()
     got = {k: v.detach().cpu().numpy().astype(np.float64) for k, v in grads.items()}
     g2 = rast.view("grad2d", torch.float64, 9 * M).cpu().numpy().reshape(9, M)
@@ -244,3 +265,26 @@ def test_benchmark_gaussian_kernel_sampled():
     say("case: workload 40 with the Gaussian kernel, no AGS, depth chunks 7")
     _sampled_parity(40, views=(3,), tiles_per_view=5, seed=41, kernel="gaussian", lambda_=1.0,
                     ags=False)
+
+
+def test_paper_scale_single_view_sampled():
+    """Workload 4: the 3.2M-splat SH3 scene in one 1920x1080 view at z = -3,
+    the heaviest per-view list (about 2.1e8 intersections), rendered alone."""
+    say("case: workload 4 (3.2M splats SH3, one 1920x1080 view), AGS, depth chunks 7")
+    _sampled_parity(4, views=(0,), tiles_per_view=10, seed=4)
+
+
+def test_benchmark_configuration_graph_replay_sampled():
+    """The headline path: workload 40 in the benchmark's configuration, the
+    whole step captured in a HIP graph and replayed."""
+    say("case: workload 40, StepGraph replays, AGS, depth chunks 7")
+    _sampled_parity(40, views=(1, 6), tiles_per_view=4, seed=42, graph=True)
+
+
+@pytest.mark.parametrize("tile,batch", [((32, 8), 0), ((16, 8), 64)])
+def test_other_tile_shapes_full_size_sampled(tile, batch):
+    """Tile shapes and LDS batches the autotuner can choose, at full size
+    (workload 3: 1M splats, 16 uneven cameras)."""
+    say(f"case: workload 3 with {tile[0]}x{tile[1]} tiles, LDS batch {batch or 'full'}")
+    _sampled_parity(3, views=(4,), tiles_per_view=5, seed=31 + tile[1] + batch, tile=tile,
+                    batch=batch)
