@@ -216,6 +216,19 @@ __device__ __forceinline__ double wave_sum8_d(const double* v, int lane) {
   return z;
 }
 
+// Sum over the wave in every lane (all lanes active): half-wave and
+// half-row exchanges, then within each 16-lane row a rotation by 8, a
+// half-row mirror and two quad permutations.
+__device__ __forceinline__ double wave_sum_all_d(double x) {
+  x = swap32_add_d(x, x);
+  x = swap16_add_d(x, x);
+  x += dpp_move_d<0x128>(x);        // row_ror:8
+  x += dpp_move_d<0x141>(x);        // row_half_mirror
+  x += dpp_move_d<0x4E>(x);         // quad_perm [2,3,0,1]
+  x += dpp_move_d<0xB1>(x);         // quad_perm [1,0,3,2]
+  return x;
+}
+
 __device__ __forceinline__ double wave_sum_to_lane63_d(double x) {
   x += dpp_move_d<0x128>(x);
   x += dpp_move_d<0x124>(x);

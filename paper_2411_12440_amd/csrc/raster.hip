@@ -38,6 +38,7 @@ struct RasterParams {
   double inv_lam;     // 1 / lambda
   double inv_lam2;    // 1 / lambda^2
   double amin, amax, oma_max, tmin;
+  double amin_pos;    // a pair is used iff alpha >= amin_pos: alpha > 0 and alpha >= amin
   float bg0, bg1, bg2;
   int ags, ags_arg, ags_scope;
   int exp_tab;        // the AGS weight of every contributing pair can use exp_neg_tab
@@ -71,24 +72,25 @@ __device__ __forceinline__ double exp_neg(double x) {
 }
 
 // e^-x on [0, kExpTabN / kExpTabStep) from a table of e^-(j / kExpTabStep)
-// (built with exp_neg) and the Taylor series of e^-r for the remainder
-// 0 <= r < 1 / kExpTabStep to degree 7 (truncation below 6e-15).  Arguments
-// outside the range are clamped into it, so the table read stays in bounds;
-// callers use it only where every argument that matters lies inside.
+// (built with exp_neg) times e^-r for the remainder 0 <= r < 1 / kExpTabStep,
+// the latter from the degree-5 polynomial interpolating e^-r at the six
+// Chebyshev nodes of [0, 1/16] (relative error below 5e-14 on the interval).
+// Arguments above the range are clamped into it (NaN too, which fmin turns
+// into the bound) and the index is clamped at 0 from below, so the table read
+// stays in bounds; callers use it only where every argument that matters lies
+// inside.
 constexpr int kExpTabStep = 16;
 constexpr int kExpTabN = 128;
 __device__ __forceinline__ double exp_neg_tab(double x, const double* tab) {
-  x = fmin(fmax(x, 0.0), (double)kExpTabN / kExpTabStep - 0.01);   // NaN -> 0
-  const int j = (int)(x * (double)kExpTabStep);
-  const double t = fma((double)j, -1.0 / kExpTabStep, x) * -1.0;   // -r, exact
-  double p = 1.0 / 5040.0;
-  p = fma(p, t, 1.0 / 720.0);
-  p = fma(p, t, 1.0 / 120.0);
-  p = fma(p, t, 1.0 / 24.0);
-  p = fma(p, t, 1.0 / 6.0);
-  p = fma(p, t, 0.5);
-  p = fma(p, t, 1.0);
-  p = fma(p, t, 1.0);
+  x = fmin(x, (double)kExpTabN / kExpTabStep - 0.01);
+  const int j = max((int)(x * (double)kExpTabStep), 0);
+  const double r = fma((double)j, -1.0 / kExpTabStep, x);   // exact
+  double p = -0.008077218246913261;
+  p = fma(p, r, 0.041648755648710845);
+  p = fma(p, r, -0.16666608768855815);
+  p = fma(p, r, 0.4999999915303285);
+  p = fma(p, r, -0.999999999954658);
+  p = fma(p, r, 0.9999999999999607);
   return tab[j] * p;
 }
 
@@ -98,10 +100,10 @@ __device__ __forceinline__ double exp_neg_tab(double x, const double* tab) {
 // kernels take every skip/stop decision identically.
 struct PairEval {
   double D, alpha, oma;
-  double invD;   // 1 / D (meaningful only for D > 0; the forward pass ignores it)
+  double invD;   // 1 / D, 0 where D = 0 (the forward pass ignores it)
   double f;      // kernel value f(D/lambda) (alpha = o f below the clamp)
   double sx;     // raised cosine: sin(pi D/lambda), for its slope
-  bool clamped;
+  double nc;     // 1 below the alpha clamp, 0 at it (alpha does not depend on o or D there)
 };
 
 // sqrt(q) for q >= 0 (a negative q, possible only by rounding of the
@@ -113,8 +115,9 @@ struct PairEval {
 // square root.
 __device__ __forceinline__ double sqrt_nonneg(double q, double* inv) {
   const double y = (double)__builtin_amdgcn_rsqf((float)q);
-  *inv = y * fma(-0.5 * q, y * y, 1.5);
-  if (!(q > 1e-30)) return 0.0;
+  const bool pos = q > 1e-30;
+  *inv = pos ? y * fma(-0.5 * q, y * y, 1.5) : 0.0;   // no slope at the apex
+  if (!pos) return 0.0;
   const double d0 = q * y;
   return fma(0.5 * y, fma(-d0, d0, q), d0);
 }
@@ -167,11 +170,10 @@ __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterPa
     e.alpha = o * e.f;
     e.oma = 1.0 - e.alpha;
   }
-  e.clamped = e.alpha > rp.amax;
-  if (e.clamped) {
-    e.alpha = rp.amax;
-    e.oma = rp.oma_max;
-  }
+  const bool clamped = e.alpha > rp.amax;
+  e.alpha = fmin(e.alpha, rp.amax);
+  e.oma = clamped ? rp.oma_max : e.oma;
+  e.nc = clamped ? 0.0 : 1.0;
   return e;
 }
 
@@ -404,7 +406,7 @@ void raster_fwd_kernel(
           const double q = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
           if (!(q < rp.qmax)) continue;
           const PairEval e = pair_eval<KF>(q, (double)st.o[k], rp, s_exptab);
-          if (!(e.alpha > 0.0) || e.alpha < rp.amin) continue;
+          if (!(e.alpha >= rp.amin_pos)) continue;
           const double Tn = T[j] * e.oma;
           if (Tn < rp.tmin) {
             done[j] = true;
@@ -462,7 +464,18 @@ void raster_fwd_kernel(
   }
 }
 
-template <int TW, int TH, int KF>
+// Adaptive gradient scaling in the backward kernel, a template parameter:
+// off; or the weight from the LDS table (exp_neg_tab, every contributing
+// pair's exponent in its range) or from the series (exp_neg), each with
+// omega applied to the geometric gradient only or to every gradient of the
+// pair.
+enum { kAgsOff = 0, kAgsTabGeo = 1, kAgsTabWhole = 2, kAgsSeriesGeo = 3, kAgsSeriesWhole = 4 };
+template <int AG>
+constexpr bool ags_table() { return AG == kAgsTabGeo || AG == kAgsTabWhole; }
+template <int AG>
+constexpr bool ags_whole() { return AG == kAgsTabWhole || AG == kAgsSeriesWhole; }
+
+template <int TW, int TH, int KF, int AG>
 __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all,
     int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
@@ -488,7 +501,7 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   __shared__ double s_exptab[kExpTabN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (kernel_uses_exp<KF>() || (rp.ags && rp.exp_tab))
+  if (kernel_uses_exp<KF>() || ags_table<AG>())
     for (int i = tid; i < kExpTabN; i += NTB) s_exptab[i] = exp_neg((double)i / kExpTabStep);
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int c = cam_of_tile(cams, C, tile);
@@ -558,6 +571,14 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
 #pragma unroll
   for (int w = 0; w < NWB; ++w) maxlast = s_max[w] > maxlast ? s_max[w] : maxlast;
   const int32_t wave_last = mx;   // entries at or beyond it concern no pixel of this wave
+  // factor of the wave sum that lane 8g holds (field wave_sum8_field(g)):
+  // the centre terms and the off-diagonal covariance term were summed
+  // without their -2, the diagonal covariance terms without their -1
+  double fac;
+  {
+    const int f = wave_sum8_field((lane >> 3) & 7);
+    fac = (f == 2 || f == 4) ? -1.0 : (f < 5 ? -2.0 : 1.0);
+  }
   static_assert(NS <= 128, "two staged entries per lane when trimming a batch");
 
   const int bsz = batch < NS ? batch : NS;
@@ -584,8 +605,8 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
       kend = __popcll(__builtin_amdgcn_ballot_w64(b0)) + __popcll(__builtin_amdgcn_ballot_w64(b1));
     }
     for (int k = kend - 1; k >= 0; --k) {
-      // Evaluated for every lane and masked at the end, so that the wave
-      // runs one path; a wave with no contributing pixel skips the entry.
+      // Evaluated for every lane and masked, so that the wave runs one path;
+      // a wave with no contributing pixel skips the entry.
       const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
       const double qd = st.qd[k], qe = st.qe[k], qf = st.qf[k];
       const int32_t pos = st.pos[k];
@@ -598,80 +619,77 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
       for (int j = 0; j < PPL; ++j) {
         qq[j] = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
         e[j] = pair_eval<KF>(qq[j], o, rp, s_exptab);
-        contrib[j] = pos < mylast[j] && qq[j] < rp.qmax && e[j].alpha > 0.0 &&
-                     e[j].alpha >= rp.amin;
+        contrib[j] = pos < mylast[j] && qq[j] < rp.qmax && e[j].alpha >= rp.amin_pos;
         any = any || contrib[j];
       }
       if (__builtin_amdgcn_ballot_w64(any) == 0ull) continue;
       const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
-      const double A = qa, B = 0.5 * qb, Cc = qc;
+      const double A = qa, B = 0.5 * qb, Cc = qc, hd = 0.5 * qd, he = 0.5 * qe;
       const double nol = -0.5 * o * rp.inv_lam;
       double gv[kGrad2d];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.0;
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
-        // transmittance, G . suffix colour and dL/dalpha (they carry the
+        // Transmittance, G . suffix colour and dL/dalpha (they carry the
         // error of every step), the per-pair terms and their sums: all FP64.
         // dL/dalpha = (T G.c - G.S) / (1 - alpha) with T the transmittance
-        // behind the splat; G.S then takes the splat's share w G.c.
-        const double inv = rcp_d(e[j].oma);
+        // behind the splat; G.S then takes the splat's share w G.c.  A
+        // masked pair gets inv = 0, which zeroes w, dL/dalpha and with them
+        // every term it would add.
+        const double inv = contrib[j] ? rcp_d(e[j].oma) : 0.0;
         const double Ti = T[j] * inv;
         const double w = e[j].alpha * Ti;
         const double GdC = G0[j] * cr + G1[j] * cg + G2[j] * cb;
         const double dLda = fma(T[j], GdC, -GS[j]) * inv;
-        GS[j] = contrib[j] ? fma(w, GdC, GS[j]) : GS[j];
+        GS[j] = fma(w, GdC, GS[j]);
         T[j] = contrib[j] ? Ti : T[j];
         double om = 1.0;
-        if (rp.ags) {
+        if constexpr (AG != kAgsOff) {
           const double xa = qq[j] * rp.ags_scale;
-          om = rp.exp_tab ? exp_neg_tab(xa, s_exptab) : exp_neg(xa);
+          om = ags_table<AG>() ? exp_neg_tab(xa, s_exptab) : exp_neg(xa);
         }
         // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
         // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the
         // conic) is what the projection backward differentiates, so its
         // gradient is summed here; going through the inverse after the sum
-        // would amplify the sum's rounding for elongated splats.
-        // The masks act on the per-pair factors (gq, the opacity factor and
-        // w), so that a masked pair adds exact zeros to the sums.
+        // would amplify the sum's rounding for elongated splats.  The factors
+        // -2 and -1 are applied to the wave sums.
         // dL/dq = dL/dalpha o f'(q): linear -omega / (2 lambda D); Gaussian
         // -f / (2 lambda^2); quadratic -1 / lambda^2; Laplacian
         // -f / (2 lambda D); raised cosine -pi sin(pi D/lambda) / (4 lambda D)
-        // (the kernels with D in f' take no gradient at D = 0)
-        constexpr bool needs_d = KF == LS_KERNEL_LINEAR || KF == LS_KERNEL_LAPLACIAN ||
-                                 KF == LS_KERNEL_COSINE;
-        const bool geo = contrib[j] && !e[j].clamped && (!needs_d || e[j].D > 0.0);
+        // (invD is 0 at D = 0: no slope at the apex).  No geometric gradient
+        // at the alpha clamp (nc = 0).
         double gq;
-        if constexpr (KF == LS_KERNEL_LINEAR) gq = nol * dLda * om * e[j].invD;
-        else if constexpr (KF == LS_KERNEL_GAUSSIAN) gq = -(dLda * e[j].alpha) * rp.ghalf;
-        else if constexpr (KF == LS_KERNEL_QUADRATIC) gq = -(o * dLda) * rp.inv_lam2;
+        if constexpr (KF == LS_KERNEL_LINEAR) gq = (nol * e[j].nc) * dLda * om * e[j].invD;
+        else if constexpr (KF == LS_KERNEL_GAUSSIAN) gq = -(dLda * e[j].alpha) * (rp.ghalf * e[j].nc);
+        else if constexpr (KF == LS_KERNEL_QUADRATIC) gq = -(o * dLda) * (rp.inv_lam2 * e[j].nc);
         else if constexpr (KF == LS_KERNEL_LAPLACIAN)
-          gq = -0.5 * (dLda * e[j].alpha) * rp.inv_lam * e[j].invD;
-        else gq = -0.7853981633974483 * (o * dLda) * rp.inv_lam * e[j].sx * e[j].invD;   // pi/4
-        gq = geo ? gq : 0.0;
+          gq = -0.5 * (dLda * e[j].alpha) * (rp.inv_lam * e[j].nc) * e[j].invD;
+        else gq = -0.7853981633974483 * (o * dLda) * (rp.inv_lam * e[j].nc) * e[j].sx * e[j].invD;
         // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
-        const double ux = fma(A, lx, fma(B, ly[j], 0.5 * qd));
-        const double uy = fma(B, lx, fma(Cc, ly[j], 0.5 * qe));
+        const double ux = fma(A, lx, fma(B, ly[j], hd));
+        const double uy = fma(B, lx, fma(Cc, ly[j], he));
         const double gux = gq * ux, guy = gq * uy;
-        const double sc = rp.ags_scope ? om : 1.0;
-        gv[0] = fma(-2.0, gux, gv[0]);
-        gv[1] = fma(-2.0, guy, gv[1]);
-        gv[2] = fma(-gux, ux, gv[2]);
-        gv[3] = fma(-2.0 * gux, uy, gv[3]);
-        gv[4] = fma(-guy, uy, gv[4]);
-        const double go = (contrib[j] && !e[j].clamped) ? dLda * sc : 0.0;
+        gv[0] += gux;                    // x -2
+        gv[1] += guy;                    // x -2
+        gv[2] = fma(gux, ux, gv[2]);     // x -1
+        gv[3] = fma(gux, uy, gv[3]);     // x -2
+        gv[4] = fma(guy, uy, gv[4]);     // x -1
+        // opacity and colour: scaled by omega only under the whole-pair scope
+        const double go = ags_whole<AG>() ? dLda * e[j].nc * om : dLda * e[j].nc;
         gv[5] = fma(e[j].f, go, gv[5]);
-        const double wsc = contrib[j] ? w * sc : 0.0;
-        gv[6] += wsc * G0[j];
-        gv[7] += wsc * G1[j];
-        gv[8] += wsc * G2[j];
+        const double ws = ags_whole<AG>() ? w * om : w;
+        gv[6] = fma(ws, G0[j], gv[6]);
+        gv[7] = fma(ws, G1[j], gv[7]);
+        gv[8] = fma(ws, G2[j], gv[8]);
       }
       // wave-wide FP64 sums (all lanes active here), one LDS add per wave
       static_assert(kGrad2d == 9, "eight fields summed together, one alone");
-      // lanes 8g hold fields 0..7 and lane 63 field 8: one LDS add at
-      // lane-dependent addresses
-      const double s8 = wave_sum8_d(gv, lane);
-      const double s1 = wave_sum_to_lane63_d(gv[8]);
+      // lanes 8g hold fields 0..7 (times their factor) and lane 63 field 8:
+      // one LDS add at lane-dependent addresses
+      const double s8 = wave_sum8_d(gv, lane) * fac;
+      const double s1 = wave_sum_all_d(gv[8]);
       const bool top = lane == 63;
       const double sv = top ? s1 : s8;
       if (((lane & 7) == 0 || top) && sv != 0.0)
@@ -724,6 +742,7 @@ RasterParams make_params(const ls_config* cfg) {
   rp.inv_lam2 = rp.inv_lam * rp.inv_lam;
   rp.ghalf = 0.5 * rp.inv_lam2;
   rp.amin = cfg->alpha_min;
+  rp.amin_pos = rp.amin > 0.0 ? rp.amin : 4.9406564584124654e-324;   // smallest positive double
   rp.amax = cfg->alpha_max;
   rp.oma_max = 1.0 - (double)cfg->alpha_max;
   rp.tmin = cfg->t_min;
@@ -829,17 +848,29 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     }
     dim3 grid((unsigned)p.T);
     ProfScope ps("raster_bwd", s);
-#define LS_BWD(TW_, TH_, KF_)                                                                      \
-  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_>), grid, dim3(raster_threads<TW_, TH_>()), 0, \
-                     s, cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,         \
+    // AGS is defined for the linear kernel only (checked by the entry point)
+    const int ag = !cfg->ags ? kAgsOff
+                   : rp.exp_tab ? (cfg->ags_scope ? kAgsTabWhole : kAgsTabGeo)
+                                : (cfg->ags_scope ? kAgsSeriesWhole : kAgsSeriesGeo);
+#define LS_BWD(TW_, TH_, KF_, AG_)                                                                 \
+  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_, AG_>), grid, dim3(raster_threads<TW_, TH_>()), \
+                     0, s, cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,      \
                      (const double*)(ws + p.t64), last, dL_dimage, dL_dalpha, grad2d, partial, det_slot)
 #define LS_BWD_K(TW_, TH_)                                                                         \
   switch (cfg->kernel) {                                                                           \
-    case LS_KERNEL_GAUSSIAN: LS_BWD(TW_, TH_, LS_KERNEL_GAUSSIAN); break;                          \
-    case LS_KERNEL_LAPLACIAN: LS_BWD(TW_, TH_, LS_KERNEL_LAPLACIAN); break;                        \
-    case LS_KERNEL_COSINE: LS_BWD(TW_, TH_, LS_KERNEL_COSINE); break;                              \
-    case LS_KERNEL_QUADRATIC: LS_BWD(TW_, TH_, LS_KERNEL_QUADRATIC); break;                        \
-    default: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR); break;                                           \
+    case LS_KERNEL_GAUSSIAN: LS_BWD(TW_, TH_, LS_KERNEL_GAUSSIAN, kAgsOff); break;                 \
+    case LS_KERNEL_LAPLACIAN: LS_BWD(TW_, TH_, LS_KERNEL_LAPLACIAN, kAgsOff); break;               \
+    case LS_KERNEL_COSINE: LS_BWD(TW_, TH_, LS_KERNEL_COSINE, kAgsOff); break;                     \
+    case LS_KERNEL_QUADRATIC: LS_BWD(TW_, TH_, LS_KERNEL_QUADRATIC, kAgsOff); break;               \
+    default:                                                                                       \
+      switch (ag) {                                                                                \
+        case kAgsTabGeo: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsTabGeo); break;                    \
+        case kAgsTabWhole: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsTabWhole); break;                \
+        case kAgsSeriesGeo: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsSeriesGeo); break;              \
+        case kAgsSeriesWhole: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsSeriesWhole); break;          \
+        default: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsOff); break;                               \
+      }                                                                                            \
+      break;                                                                                       \
   }
     if (cfg->tile_w == 16 && cfg->tile_h == 16) LS_BWD_K(16, 16)
     else if (cfg->tile_w == 16 && cfg->tile_h == 8) LS_BWD_K(16, 8)
