@@ -90,11 +90,12 @@ typedef enum {
  * bg         Background colour added as T_final * bg.
  * sh_degree  Degree 0..3 of the real spherical-harmonics colour.
  * tile_w, tile_h  Tile shape in pixels: 16x16, 16x8, 8x8 or 32x8.
- * batch      Splats staged in LDS per batch in the raster kernels: 0 (as
- *            many as the kernel has threads), 64, 128 or 256; must not
- *            exceed the tile's pixel count.  The kernels stage at most one
- *            splat per thread: a tile of 128 or more pixels runs two pixels
- *            per thread, and the backward pass stages at most 128.
+ * batch      Splats staged in LDS per batch by the forward kernel: 0 (one
+ *            per thread), 64 or 128, at most the forward kernel's threads
+ *            (the tile's pixels, halved from 128 pixels up, where each
+ *            thread composites two pixels): 128 for 16x16 and 32x8, 64 for
+ *            16x8 and 8x8.  The backward kernel runs one wave per tile and
+ *            stages min(batch, 64) (64 for batch 0).
  * depth_chunks  0 or 1: ls_bin_sort builds every tile's complete list.
  *            K in 2..12: ls_bin_sort only orders the pairs by depth and scans
  *            their tile counts; ls_rasterize_fwd then builds the lists in K

@@ -67,9 +67,14 @@ static ls_status check_config(const ls_config* c) {
                 c->tile_w, c->tile_h);
   if (c->depth_chunks < 0 || c->depth_chunks > kMaxDepthChunks)
     return fail(LS_ERR_INVALID_ARG, "depth_chunks must be 0..%d", kMaxDepthChunks);
-  int pix = c->tile_w * c->tile_h;
-  if (!(c->batch == 0 || c->batch == 64 || c->batch == 128 || c->batch == 256) || c->batch > pix)
-    return fail(LS_ERR_INVALID_ARG, "batch must be 0, 64, 128 or 256 and at most the tile's pixels");
+  // the forward kernel stages at most one entry per thread (two pixels per
+  // thread from 128 pixels up), the backward kernel one per lane of its wave
+  const int pix = c->tile_w * c->tile_h;
+  const int stage_cap = pix >= 128 ? pix / 2 : pix;
+  if (!(c->batch == 0 || c->batch == 64 || c->batch == 128) || c->batch > stage_cap)
+    return fail(LS_ERR_INVALID_ARG,
+                "batch must be 0, 64 or 128 and at most %d for %dx%d tiles (entries staged per "
+                "batch by the forward pass)", stage_cap, c->tile_w, c->tile_h);
   return LS_OK;
 }
 

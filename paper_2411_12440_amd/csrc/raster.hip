@@ -475,8 +475,18 @@ constexpr bool ags_table() { return AG == kAgsTabGeo || AG == kAgsTabWhole; }
 template <int AG>
 constexpr bool ags_whole() { return AG == kAgsTabWhole || AG == kAgsSeriesWhole; }
 
+// Backward kernel: one wave per tile, TW * TH / 64 pixels per lane.  Lane l
+// owns column l % TW; its pixels come in groups of (up to) two vertically
+// adjacent ones, one group per horizontal band of the tile (a 16x16 tile:
+// rows 2r, 2r + 1 in the upper band and 2r + 8, 2r + 9 in the lower, with
+// r = l / 16).  One read of a staged entry and one wave-wide reduction of
+// its nine gradient sums serve the whole tile; a band whose pixels all lie
+// past the entry, or of which no pixel takes the entry, skips it.
+template <int TW, int TH>
+constexpr int bwd_ppl() { return TW * TH / 64; }
+
 template <int TW, int TH, int KF, int AG>
-__global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
+__global__ __launch_bounds__(64) void raster_bwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all,
     int64_t T_all, int K, const int64_t* __restrict__ chunk_base,
     const uint32_t* __restrict__ vals, const ProjRec* __restrict__ proj, int64_t M, int batch,
@@ -484,25 +494,19 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_dalpha,
     double* __restrict__ grad2d, double* __restrict__ partial,
     const uint32_t* __restrict__ det_slot) {
-  constexpr int PPL = raster_ppl<TW, TH>();
-  constexpr int NTB = raster_threads<TW, TH>();
-  constexpr int NWB = NTB / 64;
-  // With at most two waves per tile, the LDS sums of a staged entry (two adds
-  // onto zero) do not depend on the order of the waves' atomics, so a tile's
-  // per-entry sums are reproducible; the deterministic mode relies on it.
-  static_assert(NWB <= 2, "per-tile sums are order-independent for at most two waves");
-  // at most 128 entries per batch, so that the FP64 accumulators fit beside
-  // the staged entries without lowering the occupancy
-  constexpr int NS = NTB < 128 ? NTB : 128;
-  __shared__ Stage<NS, NWB> st;
-  __shared__ double s_acc[NS][kGrad2d];   // per staged entry
-  __shared__ int32_t s_max[NWB];
+  constexpr int PPL = bwd_ppl<TW, TH>();
+  constexpr int PB = PPL < 2 ? PPL : 2;   // pixels per group (vertical neighbours)
+  constexpr int NG = PPL / PB;            // groups: horizontal bands of the tile
+  constexpr int NS = 64;                  // staged entries per batch, one per lane
+  static_assert(PPL >= 1 && (TW * TH) % 64 == 0 && 64 % TW == 0 && TH % (NG * PB) == 0,
+                "tile shape");
+  __shared__ Stage<NS, 1> st;
   __shared__ int64_t s_segbase[kMaxDepthChunks];
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   __shared__ double s_exptab[kExpTabN];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x;
   if (kernel_uses_exp<KF>() || ags_table<AG>())
-    for (int i = tid; i < kExpTabN; i += NTB) s_exptab[i] = exp_neg((double)i / kExpTabStep);
+    for (int i = lane; i < kExpTabN; i += 64) s_exptab[i] = exp_neg((double)i / kExpTabStep);
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int c = cam_of_tile(cams, C, tile);
   const CamInfo& ci = cams[c];
@@ -510,7 +514,7 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   const int ty = (int)(local / ci.GX), tx = (int)(local % ci.GX);
   const double x0c = (double)(tx * TW) + 0.5, y0c = (double)(ty * TH) + 0.5;
   // the tile's list: its segments of every chunk, in chunk order
-  if (tid == 0) {
+  if (lane == 0) {
     int32_t pre = 0;
     for (int cc = 0; cc < K; ++cc) {
       const int64_t* r = ranges_all + (int64_t)cc * (T_all + 1);
@@ -526,51 +530,57 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
   // per pixel of this lane: position, upstream gradients, transmittance and
   // the upstream gradient's dot product with the suffix colour behind the
   // current splat
-  const int lxi = tid % TW;
-  double lx = (double)lxi, ly[PPL];
-  double T[PPL], G0[PPL], G1[PPL], G2[PPL], GS[PPL];
+  const int lxi = lane % TW, rg = lane / TW;
+  const double lx = (double)lxi;
+  // the upstream gradient is kept in FP32 (as given) and widened where used
+  double ly[PPL], T[PPL], GS[PPL];
+  float G0[PPL], G1[PPL], G2[PPL];
   int32_t mylast[PPL];
-  int32_t mx = 0;
+  int32_t glast[NG];
 #pragma unroll
-  for (int j = 0; j < PPL; ++j) {
-    const int lyi = (tid / TW) * PPL + j;
-    ly[j] = (double)lyi;
-    const int px = tx * TW + lxi, py = ty * TH + lyi;
-    T[j] = 1.0;
-    G0[j] = G1[j] = G2[j] = 0.0;
-    double GA = 0.0;
-    mylast[j] = 0;
-    if (px < ci.W && py < ci.H) {
-      const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
-      const int64_t plane = (int64_t)ci.W * ci.H;
-      const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
-      // FP64: with t_min = 0 a pixel's final transmittance can fall below
-      // the FP32 range, and every T_i is recovered from it by division
-      T[j] = t64[pix];
-      const int32_t l = last[pix];
-      mylast[j] = l < 0 ? 0 : (l > len ? (int32_t)len : l);
-      G0[j] = dL_dimage[ib];
-      G1[j] = dL_dimage[ib + plane];
-      G2[j] = dL_dimage[ib + 2 * plane];
-      if (dL_dalpha) GA = dL_dalpha[pix];
+  for (int g = 0; g < NG; ++g) {
+    glast[g] = 0;
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      const int j = g * PB + i;
+      const int lyi = g * (TH / NG) + PB * rg + i;
+      ly[j] = (double)lyi;
+      const int px = tx * TW + lxi, py = ty * TH + lyi;
+      T[j] = 1.0;
+      G0[j] = G1[j] = G2[j] = 0.f;
+      double GA = 0.0;
+      mylast[j] = 0;
+      if (px < ci.W && py < ci.H) {
+        const int64_t pix = ci.pix_off + (int64_t)py * ci.W + px;
+        const int64_t plane = (int64_t)ci.W * ci.H;
+        const int64_t ib = 3 * ci.pix_off + (int64_t)py * ci.W + px;
+        // FP64: with t_min = 0 a pixel's final transmittance can fall below
+        // the FP32 range, and every T_i is recovered from it by division
+        T[j] = t64[pix];
+        const int32_t l = last[pix];
+        mylast[j] = l < 0 ? 0 : (l > len ? (int32_t)len : l);
+        G0[j] = dL_dimage[ib];
+        G1[j] = dL_dimage[ib + plane];
+        G2[j] = dL_dimage[ib + 2 * plane];
+        if (dL_dalpha) GA = dL_dalpha[pix];
+      }
+      // G . S for the suffix colour S behind the current splat, which starts
+      // as the background term T_final bg; the accumulated opacity
+      // 1 - T_final is a fourth channel with splat colour 0 and background -1
+      GS[j] = T[j] * ((double)G0[j] * (double)rp.bg0 + (double)G1[j] * (double)rp.bg1 +
+                      (double)G2[j] * (double)rp.bg2 - GA);
+      glast[g] = mylast[j] > glast[g] ? mylast[j] : glast[g];
     }
-    // G . S for the suffix colour S behind the current splat, which starts
-    // as the background term T_final bg; the accumulated opacity
-    // 1 - T_final is a fourth channel with splat colour 0 and background -1
-    GS[j] = T[j] * (G0[j] * (double)rp.bg0 + G1[j] * (double)rp.bg1 + G2[j] * (double)rp.bg2 - GA);
-    mx = mylast[j] > mx ? mylast[j] : mx;
+    // band-wide maximum of `last`: entries at or beyond it concern no pixel
+    // of the band
+    for (int d = 32; d > 0; d >>= 1) {
+      const int32_t y = __shfl_xor(glast[g], d, 64);
+      glast[g] = y > glast[g] ? y : glast[g];
+    }
   }
-  // tile-wide maximum of `last`
-  for (int d = 32; d > 0; d >>= 1) {
-    int32_t y = __shfl_xor(mx, d, 64);
-    mx = y > mx ? y : mx;
-  }
-  if (lane == 0) s_max[wave] = mx;
-  __syncthreads();
-  int32_t maxlast = 0;
+  int32_t tile_last = 0;
 #pragma unroll
-  for (int w = 0; w < NWB; ++w) maxlast = s_max[w] > maxlast ? s_max[w] : maxlast;
-  const int32_t wave_last = mx;   // entries at or beyond it concern no pixel of this wave
+  for (int g = 0; g < NG; ++g) tile_last = glast[g] > tile_last ? glast[g] : tile_last;
   // factor of the wave sum that lane 8g holds (field wave_sum8_field(g)):
   // the centre terms and the off-diagonal covariance term were summed
   // without their -2, the diagonal covariance terms without their -1
@@ -579,142 +589,134 @@ __global__ __launch_bounds__((raster_threads<TW, TH>())) void raster_bwd_kernel(
     const int f = wave_sum8_field((lane >> 3) & 7);
     fac = (f == 2 || f == 4) ? -1.0 : (f < 5 ? -2.0 : 1.0);
   }
-  static_assert(NS <= 128, "two staged entries per lane when trimming a batch");
+  const bool top = lane == 63;
+  const int my_field = top ? 8 : wave_sum8_field(lane >> 3);
+  const bool holder = (lane & 7) == 0 || top;   // lanes that end with a field's sum
 
   const int bsz = batch < NS ? batch : NS;
-  for (int32_t hi = maxlast; hi > 0; hi -= bsz) {
+  for (int32_t hi = tile_last; hi > 0; hi -= bsz) {
     const int32_t lo = hi - bsz > 0 ? hi - bsz : 0;
-    __syncthreads();
-    const int32_t q = lo + tid;
+    __syncthreads();   // the previous batch's entries are no longer read
+    const int32_t q = lo + lane;
     int64_t vidx = 0;
     if (q < hi) {
       int cc = 0;
       while (cc + 1 < K && s_segpre[cc + 1] <= q) ++cc;
       vidx = s_segbase[cc] + (q - s_segpre[cc]);
     }
-    const int cnt =
-        stage_batch<TW, TH, NS, NWB>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c, rp.qmax);
-    for (int i = tid; i < kGrad2d * NS; i += NTB) (&s_acc[0][0])[i] = 0.0;
-    __syncthreads();
-    // the staged positions increase with k: the entries this wave needs are
+    const int cnt = stage_batch<TW, TH, NS, 1>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c,
+                                              rp.qmax);
+    // the staged positions increase with k: the entries the tile needs are
     // the first kend, those before its last contributor
-    int kend;
-    {
-      const bool b0 = lane < cnt && st.pos[lane] < wave_last;
-      const bool b1 = lane + 64 < cnt && st.pos[lane + 64] < wave_last;
-      kend = __popcll(__builtin_amdgcn_ballot_w64(b0)) + __popcll(__builtin_amdgcn_ballot_w64(b1));
-    }
+    const int kend =
+        __popcll(__builtin_amdgcn_ballot_w64(lane < cnt && st.pos[lane] < tile_last));
     for (int k = kend - 1; k >= 0; --k) {
-      // Evaluated for every lane and masked, so that the wave runs one path;
-      // a wave with no contributing pixel skips the entry.
       const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
       const double qd = st.qd[k], qe = st.qe[k], qf = st.qf[k];
       const int32_t pos = st.pos[k];
       const double o = (double)st.o[k];
-      double qq[PPL];
-      PairEval e[PPL];
-      bool contrib[PPL];
-      bool any = false;
-#pragma unroll
-      for (int j = 0; j < PPL; ++j) {
-        qq[j] = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
-        e[j] = pair_eval<KF>(qq[j], o, rp, s_exptab);
-        contrib[j] = pos < mylast[j] && qq[j] < rp.qmax && e[j].alpha >= rp.amin_pos;
-        any = any || contrib[j];
-      }
-      if (__builtin_amdgcn_ballot_w64(any) == 0ull) continue;
       const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
       const double A = qa, B = 0.5 * qb, Cc = qc, hd = 0.5 * qd, he = 0.5 * qe;
       const double nol = -0.5 * o * rp.inv_lam;
       double gv[kGrad2d];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.0;
+      bool used = false;
 #pragma unroll
-      for (int j = 0; j < PPL; ++j) {
-        // Transmittance, G . suffix colour and dL/dalpha (they carry the
-        // error of every step), the per-pair terms and their sums: all FP64.
-        // dL/dalpha = (T G.c - G.S) / (1 - alpha) with T the transmittance
-        // behind the splat; G.S then takes the splat's share w G.c.  A
-        // masked pair gets inv = 0, which zeroes w, dL/dalpha and with them
-        // every term it would add.
-        const double inv = contrib[j] ? rcp_d(e[j].oma) : 0.0;
-        const double Ti = T[j] * inv;
-        const double w = e[j].alpha * Ti;
-        const double GdC = G0[j] * cr + G1[j] * cg + G2[j] * cb;
-        const double dLda = fma(T[j], GdC, -GS[j]) * inv;
-        GS[j] = fma(w, GdC, GS[j]);
-        T[j] = contrib[j] ? Ti : T[j];
-        double om = 1.0;
-        if constexpr (AG != kAgsOff) {
-          const double xa = qq[j] * rp.ags_scale;
-          om = ags_table<AG>() ? exp_neg_tab(xa, s_exptab) : exp_neg(xa);
+      for (int g = 0; g < NG; ++g) {
+        if (pos >= glast[g]) continue;   // every pixel of the band stopped before it
+        // Evaluated for every lane of the band and masked, so that the wave
+        // runs one path; a band with no contributing pixel skips the entry.
+        double qq[PB];
+        PairEval e[PB];
+        bool contrib[PB];
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+          const int j = g * PB + i;
+          qq[i] = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
+          e[i] = pair_eval<KF>(qq[i], o, rp, s_exptab);
+          contrib[i] = pos < mylast[j] && qq[i] < rp.qmax && e[i].alpha >= rp.amin_pos;
+          any = any || contrib[i];
         }
-        // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
-        // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the
-        // conic) is what the projection backward differentiates, so its
-        // gradient is summed here; going through the inverse after the sum
-        // would amplify the sum's rounding for elongated splats.  The factors
-        // -2 and -1 are applied to the wave sums.
-        // dL/dq = dL/dalpha o f'(q): linear -omega / (2 lambda D); Gaussian
-        // -f / (2 lambda^2); quadratic -1 / lambda^2; Laplacian
-        // -f / (2 lambda D); raised cosine -pi sin(pi D/lambda) / (4 lambda D)
-        // (invD is 0 at D = 0: no slope at the apex).  No geometric gradient
-        // at the alpha clamp (nc = 0).
-        double gq;
-        if constexpr (KF == LS_KERNEL_LINEAR) gq = (nol * e[j].nc) * dLda * om * e[j].invD;
-        else if constexpr (KF == LS_KERNEL_GAUSSIAN) gq = -(dLda * e[j].alpha) * (rp.ghalf * e[j].nc);
-        else if constexpr (KF == LS_KERNEL_QUADRATIC) gq = -(o * dLda) * (rp.inv_lam2 * e[j].nc);
-        else if constexpr (KF == LS_KERNEL_LAPLACIAN)
-          gq = -0.5 * (dLda * e[j].alpha) * (rp.inv_lam * e[j].nc) * e[j].invD;
-        else gq = -0.7853981633974483 * (o * dLda) * (rp.inv_lam * e[j].nc) * e[j].sx * e[j].invD;
-        // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
-        const double ux = fma(A, lx, fma(B, ly[j], hd));
-        const double uy = fma(B, lx, fma(Cc, ly[j], he));
-        const double gux = gq * ux, guy = gq * uy;
-        gv[0] += gux;                    // x -2
-        gv[1] += guy;                    // x -2
-        gv[2] = fma(gux, ux, gv[2]);     // x -1
-        gv[3] = fma(gux, uy, gv[3]);     // x -2
-        gv[4] = fma(guy, uy, gv[4]);     // x -1
-        // opacity and colour: scaled by omega only under the whole-pair scope
-        const double go = ags_whole<AG>() ? dLda * e[j].nc * om : dLda * e[j].nc;
-        gv[5] = fma(e[j].f, go, gv[5]);
-        const double ws = ags_whole<AG>() ? w * om : w;
-        gv[6] = fma(ws, G0[j], gv[6]);
-        gv[7] = fma(ws, G1[j], gv[7]);
-        gv[8] = fma(ws, G2[j], gv[8]);
+        if (__builtin_amdgcn_ballot_w64(any) == 0ull) continue;
+        used = true;
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+          const int j = g * PB + i;
+          // Transmittance, G . suffix colour and dL/dalpha (they carry the
+          // error of every step), the per-pair terms and their sums: all
+          // FP64.  dL/dalpha = (T G.c - G.S) / (1 - alpha) with T the
+          // transmittance behind the splat; G.S then takes the splat's share
+          // w G.c.  A masked pair gets inv = 0, which zeroes w, dL/dalpha and
+          // with them every term it would add.
+          const double inv = contrib[i] ? rcp_d(e[i].oma) : 0.0;
+          const double Ti = T[j] * inv;
+          const double w = e[i].alpha * Ti;
+          const double g0 = G0[j], g1 = G1[j], g2 = G2[j];
+          const double GdC = g0 * cr + g1 * cg + g2 * cb;
+          const double dLda = fma(T[j], GdC, -GS[j]) * inv;
+          GS[j] = fma(w, GdC, GS[j]);
+          T[j] = contrib[i] ? Ti : T[j];
+          double om = 1.0;
+          if constexpr (AG != kAgsOff) {
+            const double xa = qq[i] * rp.ags_scale;
+            om = ags_table<AG>() ? exp_neg_tab(xa, s_exptab) : exp_neg(xa);
+          }
+          // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
+          // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the
+          // conic) is what the projection backward differentiates, so its
+          // gradient is summed here; going through the inverse after the sum
+          // would amplify the sum's rounding for elongated splats.  The
+          // factors -2 and -1 are applied to the wave sums.
+          // dL/dq = dL/dalpha o f'(q): linear -omega / (2 lambda D); Gaussian
+          // -f / (2 lambda^2); quadratic -1 / lambda^2; Laplacian
+          // -f / (2 lambda D); raised cosine -pi sin(pi D/lambda) / (4 lambda D)
+          // (invD is 0 at D = 0: no slope at the apex).  No geometric
+          // gradient at the alpha clamp (nc = 0).
+          double gq;
+          if constexpr (KF == LS_KERNEL_LINEAR) gq = (nol * e[i].nc) * dLda * om * e[i].invD;
+          else if constexpr (KF == LS_KERNEL_GAUSSIAN)
+            gq = -(dLda * e[i].alpha) * (rp.ghalf * e[i].nc);
+          else if constexpr (KF == LS_KERNEL_QUADRATIC) gq = -(o * dLda) * (rp.inv_lam2 * e[i].nc);
+          else if constexpr (KF == LS_KERNEL_LAPLACIAN)
+            gq = -0.5 * (dLda * e[i].alpha) * (rp.inv_lam * e[i].nc) * e[i].invD;
+          else
+            gq = -0.7853981633974483 * (o * dLda) * (rp.inv_lam * e[i].nc) * e[i].sx * e[i].invD;
+          // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
+          const double ux = fma(A, lx, fma(B, ly[j], hd));
+          const double uy = fma(B, lx, fma(Cc, ly[j], he));
+          const double gux = gq * ux, guy = gq * uy;
+          gv[0] += gux;                    // x -2
+          gv[1] += guy;                    // x -2
+          gv[2] = fma(gux, ux, gv[2]);     // x -1
+          gv[3] = fma(gux, uy, gv[3]);     // x -2
+          gv[4] = fma(guy, uy, gv[4]);     // x -1
+          // opacity and colour: scaled by omega only under the whole-pair scope
+          const double go = ags_whole<AG>() ? dLda * e[i].nc * om : dLda * e[i].nc;
+          gv[5] = fma(e[i].f, go, gv[5]);
+          const double ws = ags_whole<AG>() ? w * om : w;
+          gv[6] = fma(ws, g0, gv[6]);
+          gv[7] = fma(ws, g1, gv[7]);
+          gv[8] = fma(ws, g2, gv[8]);
+        }
       }
-      // wave-wide FP64 sums (all lanes active here), one LDS add per wave
+      if (!used) continue;
+      // wave-wide FP64 sums (all lanes active here): lanes 8g hold fields
+      // 0..7 (times their factor), lane 63 field 8
       static_assert(kGrad2d == 9, "eight fields summed together, one alone");
-      // lanes 8g hold fields 0..7 (times their factor) and lane 63 field 8:
-      // one LDS add at lane-dependent addresses
       const double s8 = wave_sum8_d(gv, lane) * fac;
       const double s1 = wave_sum_all_d(gv[8]);
-      const bool top = lane == 63;
       const double sv = top ? s1 : s8;
-      if (((lane & 7) == 0 || top) && sv != 0.0)
-        atomicAdd(&s_acc[k][top ? 8 : wave_sum8_field(lane >> 3)], sv);
-    }
-    __syncthreads();
-    if (tid < cnt) {
       if (partial) {
-        // deterministic mode: the entry's slot in pair order (from its
-        // position in the chunk-concatenated lists); the pair sums are
-        // formed afterwards
-        const int32_t q = st.pos[tid];
+        // deterministic mode: the tile's sums of this entry go to the
+        // entry's slot in pair order; the pair sums are formed afterwards
         int cc = 0;
-        while (cc + 1 < K && s_segpre[cc + 1] <= q) ++cc;
-        const int64_t e = s_segbase[cc] + (q - s_segpre[cc]);
-        const int64_t slot = det_slot[e];
-#pragma unroll
-        for (int f = 0; f < kGrad2d; ++f) partial[slot * kGrad2d + f] = s_acc[tid][f];
-      } else {
-        const int64_t m = (int64_t)st.m[tid];
-#pragma unroll
-        for (int f = 0; f < kGrad2d; ++f) {
-          const double v = s_acc[tid][f];
-          if (v != 0.0) unsafeAtomicAdd(grad2d + (int64_t)f * M + m, v);
-        }
+        while (cc + 1 < K && s_segpre[cc + 1] <= pos) ++cc;
+        const int64_t ent = s_segbase[cc] + (pos - s_segpre[cc]);
+        if (holder) partial[(int64_t)det_slot[ent] * kGrad2d + my_field] = sv;
+      } else if (holder && sv != 0.0) {
+        unsafeAtomicAdd(grad2d + (int64_t)my_field * M + (int64_t)st.m[k], sv);
       }
     }
   }
@@ -853,8 +855,8 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
                    : rp.exp_tab ? (cfg->ags_scope ? kAgsTabWhole : kAgsTabGeo)
                                 : (cfg->ags_scope ? kAgsSeriesWhole : kAgsSeriesGeo);
 #define LS_BWD(TW_, TH_, KF_, AG_)                                                                 \
-  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_, AG_>), grid, dim3(raster_threads<TW_, TH_>()), \
-                     0, s, cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,      \
+  hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_, AG_>), grid, dim3(64), 0, s,                \
+                     cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,      \
                      (const double*)(ws + p.t64), last, dL_dimage, dL_dalpha, grad2d, partial, det_slot)
 #define LS_BWD_K(TW_, TH_)                                                                         \
   switch (cfg->kernel) {                                                                           \

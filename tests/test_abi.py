@@ -76,6 +76,23 @@ def test_invalid_config_rejected(field, value):
     assert len(B.LIB.ls_last_error()) > 0
 
 
+@pytest.mark.parametrize("tw,th,batch,ok", [(16, 16, 128, True), (16, 16, 64, True),
+                                             (16, 16, 256, False), (16, 8, 64, True),
+                                             (16, 8, 128, False), (32, 8, 128, True),
+                                             (8, 8, 128, False), (8, 8, 0, True)])
+def test_batch_bounded_by_the_staging_capacity(tw, th, batch, ok):
+    """A batch above what the forward kernel stages per round (its threads)
+    is refused instead of being clamped."""
+    from paper_2411_12440_amd import binding as B
+    cfg = B.make_config(tile_w=tw, tile_h=th, batch=batch)
+    if ok:
+        assert B.ls_workspace_size(cfg, _cams(), 0) > 0
+    else:
+        with pytest.raises(B.LsError) as ei:
+            B.ls_workspace_size(cfg, _cams(), 0)
+        assert ei.value.status == -1 and b"staged" in B.LIB.ls_last_error()
+
+
 def test_ags_needs_the_linear_kernel():
     from paper_2411_12440_amd import binding as B
     cfg = B.make_config(ags=True, kernel="gaussian")

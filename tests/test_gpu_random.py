@@ -34,7 +34,8 @@ def draw_case(seed):
     kernel, lam = KERNELS[int(r.integers(len(KERNELS)))]
     ags = kernel == "linear" and bool(r.integers(2))
     tw, th = TILES[int(r.integers(len(TILES)))]
-    batches = [b for b in (0, 64, 128, 256) if b <= tw * th]
+    cap = tw * th // 2 if tw * th >= 128 else tw * th    # forward threads per tile
+    batches = [b for b in (0, 64, 128) if b <= cap]
     case = dict(
         n_scenes=int(r.integers(1, 3)),
         n=[int(r.integers(1, 900)) for _ in range(2)],
