@@ -152,58 +152,180 @@ def read_traffic(kernel):
 
 
 # --------------------------------------------------------------------------
-# CPU baseline: the FP64 oracle on a bounded sample
+# CPU baseline: the FP64 oracle on one view, across the host cores
 # --------------------------------------------------------------------------
 
-def cpu_baseline(scene, cams, n_tiles_sample=6):
+def _cpu_workers() -> int:
+    """Worker processes for the oracle: the cores this process may run on,
+    at most 16 (a one-GPU machine's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_CPU = {}   # the view's oracle state, inherited by the forked workers
+
+
+def _cpu_tiles(tiles):
+    """Forward composite and reverse pass of the given tiles (oracle);
+    seconds per tile."""
+    import numpy as np
+
+    from oracle import composite
+    g = _CPU
+    W, H, p = g["W"], g["H"], g["p"]
+    out = []
+    for t in tiles:
+        t1 = time.perf_counter()
+        ids = g["ids"][g["ranges"][t]:g["ranges"][t + 1]]
+        ty, tx = divmod(int(t), g["gx"])
+        px, py = composite._tile_pixels(tx, ty, W, H, g["cfg"])
+        res = composite.composite_tile(ids, px, py, p["mean2d"], p["conic"], g["opac"], p["rgb"],
+                                       g["cfg"], want_pairs=True)
+        Gt = np.stack([g["G"][ch * W * H + py * W + px] for ch in range(3)], 1).astype(np.float64)
+        composite.reverse_tile(res, Gt, p["mean2d"], p["conic"], g["opac"], p["rgb"], g["cfg"],
+                               g["n"])
+        out.append(time.perf_counter() - t1)
+    return out
+
+
+def _cpu_project_bwd(span):
+    """Projection backward of the splats [a, b) (oracle)."""
+    import numpy as np
+
+    from oracle import projection
+    g = _CPU
+    a, b = span
+    sub = {k: (v[a:b] if isinstance(v, np.ndarray) and v.shape[:1] == (g["n"],) else v)
+           for k, v in g["p"].items()}
+    n = b - a
+    rs = np.random.default_rng(a)
+    projection.project_backward(sub, g["sh"][a:b], g["deg"], rs.normal(size=(n, 2)),
+                                rs.normal(size=(n, 3)), rs.normal(size=(n, 3)))
+    return n
+
+
+def cpu_baseline_child(n_splats: int, per_stratum: int = 32, strata: int = 8, seed: int = 5):
+    """One 1920x1080 view of the benchmark scene through the FP64 oracle, in a
+    process that has not touched the GPU (its workers are forked from it).
+    Projection, FP32 binning, key generation and the (tile, depth, id) sort of
+    the whole view run as the oracle runs them, on one core.  The forward and
+    reverse composite of the view's tiles is measured on a stratified sample
+    (strata: quantiles of the tile-list length; per_stratum tiles from each)
+    spread over the worker processes, and extrapolated to every tile with the
+    stratified estimator, whose standard error is reported.  The projection
+    backward of every splat runs split over the workers."""
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
-    from oracle import RasterConfig, binning, composite, projection
+    from oracle import RasterConfig, binning, projection
     from oracle.render import layout
     from paper_2411_12440_amd import scenes as S
 
+    workers = _cpu_workers()
+    scene, views = make_workload(n_splats, 8)
+    cams = views.subset([0])
     cfg = RasterConfig(ags=True)
-    c = 0
-    W, H = int(cams.width[c]), int(cams.height[c])
+    W, H = int(cams.width[0]), int(cams.height[0])
+    lay = layout(np.array([0, scene.n]), cams, cfg)
+    gx, gy = lay.grid[0]
+    ctx = mp.get_context("fork")
     with threadpool_limits(1):
+        log(f"cpu baseline: oracle on one {W}x{H} view, {workers} worker processes")
         t0 = time.perf_counter()
-        rect, nt, dk = binning.binning_fp32(scene.means, scene.scales, scene.quats, cams.viewmat[c],
-                                            cams.intrin[c], W, H, cfg)
         p = projection.project(scene.means, scene.scales, scene.quats, scene.sh, scene.sh_degree,
-                               cams.viewmat[c], cams.intrin[c], W, H, cfg)
+                               cams.viewmat[0], cams.intrin[0], W, H, cfg)
+        rect, nt, dk = binning.binning_fp32(scene.means, scene.scales, scene.quats,
+                                            cams.viewmat[0], cams.intrin[0], W, H, cfg)
         t_proj = time.perf_counter() - t0
-        one = cams.subset([c])
-        lay = layout(np.array([0, scene.n]), one, cfg)
-        gx, gy = lay.grid[0]
-        rng = np.random.default_rng(5)
-        tiles = rng.choice(gx * gy, n_tiles_sample, replace=False)
-        G = S.upstream_grad(one, 7004)
-        opac = scene.opacity.astype(np.float64)
-        t_tiles = 0.0
-        acc = [np.zeros((scene.n, 3)), np.zeros(scene.n), np.zeros((scene.n, 3)), np.zeros((scene.n, 2))]
-        for t in tiles:
-            t1 = time.perf_counter()
-            ids = binning.tile_list(rect, nt, dk, int(t), lay)
-            ty, tx = divmod(int(t), gx)
-            px, py = composite._tile_pixels(tx, ty, W, H, cfg)
-            res = composite.composite_tile(ids, px, py, p["mean2d"], p["conic"], opac, p["rgb"], cfg,
-                                           want_pairs=True)
-            Gt = np.stack([G[ch * W * H + py * W + px] for ch in range(3)], 1).astype(np.float64)
-            r = composite.reverse_tile(res, Gt, p["mean2d"], p["conic"], opac, p["rgb"], cfg, scene.n)
-            for a, b in zip(acc, r):
-                a += b
-            t_tiles += time.perf_counter() - t1
-        t1 = time.perf_counter()
-        projection.project_backward(p, scene.sh, scene.sh_degree, acc[3], acc[2], acc[0])
-        t_pbwd = time.perf_counter() - t1
-    per_view = t_proj + t_tiles / n_tiles_sample * (gx * gy) + t_pbwd
+        t0 = time.perf_counter()
+        g_, d_, i_ = binning.intersections_array(rect, nt, dk, np.arange(scene.n), 0, gx)
+        g_, d_, i_ = binning.sort_arrays(g_, d_, i_)
+        ranges = binning.tile_ranges(g_, gx * gy)
+        t_sort = time.perf_counter() - t0
+        n_isect = int(len(i_))
+        del g_, d_, rect, nt, dk
+        log(f"cpu baseline: projection + binning {t_proj:.1f} s, keys + sort of {n_isect} "
+            f"intersections {t_sort:.1f} s")
+        # stratified sample of tiles by list length
+        lens = np.diff(ranges)
+        edges = np.quantile(lens, np.linspace(0.0, 1.0, strata + 1))
+        stratum = np.clip(np.searchsorted(edges[1:-1], lens, side="right"), 0, strata - 1)
+        rs = np.random.default_rng(seed)
+        sample, of = [], []
+        for h in range(strata):
+            members = np.nonzero(stratum == h)[0]
+            k = min(per_stratum, len(members))
+            sample += [int(t) for t in rs.choice(members, k, replace=False)]
+            of += [h] * k
+        _CPU.update(W=W, H=H, p=p, ids=i_, ranges=ranges, gx=gx, cfg=cfg,
+                    opac=scene.opacity.astype(np.float64), n=scene.n,
+                    G=S.upstream_grad(cams, 7004), sh=scene.sh, deg=scene.sh_degree)
+        chunks = [sample[j::workers] for j in range(workers)]
+        spans = np.linspace(0, scene.n, 4 * workers + 1).astype(np.int64)
+        with ctx.Pool(workers) as pool:
+            t0 = time.perf_counter()
+            times = pool.map(_cpu_tiles, chunks)
+            wall = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            pool.map(_cpu_project_bwd, list(zip(spans[:-1], spans[1:])))
+            t_pbwd = time.perf_counter() - t0
+    per = np.zeros(len(sample))
+    for j in range(workers):
+        per[j::workers] = times[j]
+    of = np.array(of)
+    est, var = 0.0, 0.0
+    for h in range(strata):
+        Nh = int(np.sum(stratum == h))
+        x = per[of == h]
+        est += Nh * float(x.mean())
+        if len(x) > 1:
+            var += Nh * Nh * (1.0 - len(x) / Nh) * float(x.var(ddof=1)) / len(x)
+    # the tiles' seconds over the workers, at the parallel efficiency the
+    # sample itself reached
+    eff = wall / (float(per.sum()) / workers)
+    t_tiles = est / workers * eff
+    rel_se = math.sqrt(var) / est
+    per_view = t_proj + t_sort + t_tiles + t_pbwd
     mpx = W * H / per_view / 1e6
-    sample = (f"one 1920x1080 view of the 3.2M-splat scene: projection + FP32 binning of all "
-              f"splats ({t_proj:.1f} s), forward+backward composite of {n_tiles_sample} random "
-              f"16x16 tiles ({t_tiles:.1f} s, scaled to all {gx * gy} tiles), projection backward "
-              f"of all splats ({t_pbwd:.1f} s); tile-list sort excluded; extrapolated")
-    return dict(value=round(mpx, 6), unit="Mpixel/s", cores=1, kind="oracle", sample=sample)
+    sample_txt = (
+        f"one {W}x{H} view of the {scene.n}-splat scene (the first of the 8 views), FP64 oracle: "
+        f"projection + FP32 binning of every splat {t_proj:.1f} s and key generation + sort of its "
+        f"{n_isect} intersections {t_sort:.1f} s, one core each as the oracle runs them; forward + "
+        f"reverse composite of a stratified sample of {len(sample)} of the {gx * gy} tiles "
+        f"({strata} strata by list length) over {workers} processes, {wall:.1f} s wall for "
+        f"{per.sum():.1f} s of tile time, extrapolated to every tile: {t_tiles:.1f} s (relative "
+        f"standard error of the extrapolation {rel_se:.1%}); projection backward of every splat "
+        f"over {workers} processes {t_pbwd:.1f} s; {per_view:.1f} s per view")
+    return dict(value=round(mpx, 6), unit="Mpixel/s", cores=workers, kind="oracle",
+                cpu_model=_cpu_model(), nproc=os.cpu_count(), rel_std_error=round(rel_se, 4),
+                seconds_per_view=round(per_view, 2), sample=sample_txt)
+
+
+def cpu_baseline(n_splats: int):
+    """Runs cpu_baseline_child in a fresh interpreter (this process holds the
+    GPU; its forked children must not) and returns its record."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                        str(n_splats)], stdout=subprocess.PIPE, text=True, timeout=1200)
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline child failed with status {r.returncode}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 # --------------------------------------------------------------------------
@@ -273,6 +395,10 @@ def training_stages(B, S, torch, rast, sp, grads, cams, steps, warmup):
 
 
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--cpu-baseline-child":
+        # the oracle baseline in a process of its own that never touches the GPU
+        print(json.dumps(cpu_baseline_child(int(sys.argv[2]))), flush=True)
+        return
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -299,12 +425,16 @@ def main():
         from paper_2411_12440_amd import autotune
         log("bench: autotuning tile shape, LDS batch and depth chunks")
         tuner = autotune.Autotuner()
-        settings = tuner.choose(cams, off, sp, G_all, 3, ags=bool(args.ags))
+        settings = tuner.choose(cams, off, sp, G_all, 3, ags=bool(args.ags),
+                                deterministic=bool(args.deterministic))
         tuned = tuner.table.get(autotune.tune_key(torch.cuda.get_device_name(dev), scene.n,
-                                                  cams, 3))
+                                                  cams, 3, ags=bool(args.ags),
+                                                  deterministic=bool(args.deterministic)))
         log(f"bench: tuned settings {settings}")
     cfgkw = dict(sh_degree=3, ags=bool(args.ags), deterministic=bool(args.deterministic),
                  **settings)
+    from paper_2411_12440_amd.autotune import effective
+    eff = effective(settings)
     P = int(sum(int(w) * int(h) for w, h in zip(cams.width, cams.height)))
 
     # ---- batched path -------------------------------------------------------
@@ -500,8 +630,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("bench: timing the FP64 oracle on a bounded sample (host CPU)")
-        cpu = cpu_baseline(scene, cams)
+        log("bench: timing the FP64 oracle on one view (host CPU, worker processes)")
+        cpu = cpu_baseline(args.splats)
 
     out = {
         "metric": METRIC,
@@ -525,6 +655,7 @@ def main():
                    "deterministic": bool(args.deterministic),
                    "tile": f"{settings['tile_w']}x{settings['tile_h']}",
                    "lds_batch": settings["batch"],
+                   "staged_per_batch": {"forward": eff[2], "backward": eff[3]},
                    "autotuned": bool(args.tune),
                    "tuning": None if tuned is None else tuned.get("results"),
                    "parallelism": "single GPU"},
