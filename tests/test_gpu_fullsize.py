@@ -281,7 +281,7 @@ def test_benchmark_configuration_graph_replay_sampled():
     _sampled_parity(40, views=(1, 6), tiles_per_view=4, seed=42, graph=True)
 
 
-@pytest.mark.parametrize("tile,batch", [((32, 8), 0), ((16, 8), 64)])
+@pytest.mark.parametrize("tile,batch", [((32, 8), 0), ((16, 8), 64), ((16, 16), 64)])
 def test_other_tile_shapes_full_size_sampled(tile, batch):
     """Tile shapes and LDS batches the autotuner can choose, at full size
     (workload 3: 1M splats, 16 uneven cameras)."""

@@ -136,6 +136,52 @@ def test_multi_camera_multi_scene(chunks):
     compare_grads(grads, go, scene)
 
 
+@pytest.mark.parametrize("chunks", [3, 7])
+def test_chunk_lists_are_prefixes_of_complete_lists(chunks):
+    """Through the C ABI, the library against itself: with depth chunks each
+    tile's list (its chunk segments in chunk order) is a prefix of the
+    complete list that ls_bin_sort builds with one chunk, long enough to
+    reach every pixel's last contributor, and the composite (image, final_T,
+    last) is the same bit for bit."""
+    from tests.gpu_helpers import gpu_arrays, gpu_forward, tile_lists
+    say(f"case: chunk lists against complete lists, 3 scenes, 6 cameras, {chunks} chunks")
+    # large splats (log-scale N(-1.5, 0.6)): about 40% of the pixels run out
+    # of transmittance, so the chunks leave entries unbuilt
+    scs = [scenes.make_scene(n, 920 + i, -1.5, 0.6, 1) for i, n in enumerate((900, 1500, 600))]
+    scene, off = scenes.concat_scenes(scs)
+    res = [(96, 64), (130, 70), (64, 64), (200, 90), (50, 120), (128, 96)]
+    cams = scenes.sphere_cameras(6, 4.0, res, scene_of_cam=[0, 1, 2, 0, 1, 2])
+    _, g1kw = cfg_pair(depth_chunks=1, ags=True)
+    _, gkkw = cfg_pair(depth_chunks=chunks, ags=True)
+    r1, _ = gpu_forward(scene, off, cams, g1kw)
+    rk, _ = gpu_forward(scene, off, cams, gkkw)
+    g1, gk = gpu_arrays(r1), gpu_arrays(rk)
+    T = int(r1.layout.n_tiles)
+    assert T == int(rk.layout.n_tiles) and len(gk["chunk_base"]) == chunks + 1
+    L1, Lk = tile_lists(g1, T), tile_lists(gk, T)
+    # the tile each pixel belongs to, to find its tile's longest reach
+    pix_tile = []
+    for c in range(cams.n):
+        W, H = int(cams.width[c]), int(cams.height[c])
+        gx = -(-W // 16)
+        yy, xx = np.divmod(np.arange(W * H), W)
+        pix_tile.append(int(sum(-(-int(cams.width[d]) // 16) * -(-int(cams.height[d]) // 16)
+                                for d in range(c))) + (yy // 16) * gx + xx // 16)
+    pix_tile = np.concatenate(pix_tile)
+    reach = np.zeros(T, np.int64)
+    np.maximum.at(reach, pix_tile, gk["last"])
+    built = 0
+    for t in range(T):
+        assert len(Lk[t]) <= len(L1[t]), t
+        np.testing.assert_array_equal(Lk[t], L1[t][:len(Lk[t])])
+        assert len(Lk[t]) >= reach[t], t
+        built += len(Lk[t])
+    assert built == int(gk["chunk_base"][-1]) and built < int(g1["chunk_base"][-1])
+    for k in ("image", "final_T", "last"):
+        assert np.array_equal(g1[k], gk[k]), k
+    say(f"  {built} of {int(g1['chunk_base'][-1])} entries built; composites equal")
+
+
 @pytest.mark.parametrize("chunks", [1, 7])
 def test_workload2_binning_and_sampled_tiles(chunks):
     """100k splats, SH3, 1280x720: binning bit-exact; composite and
