@@ -211,6 +211,15 @@ struct Stage {
   int32_t wcount[NW];
 };
 
+// Per-entry constants only the backward kernel reads, staged beside the
+// quadratic form so that the entry loop does not recompute them per entry.
+template <int NS>
+struct StageExt {
+  double B[NS], hd[NS], he[NS];           // conic B; (qd, qe) / 2 = -(u, v) at the tile origin
+  double o[NS], r[NS], g[NS], b[NS];      // opacity and colour, widened
+  double nol[NS];                         // -o / (2 lambda)
+};
+
 // D'^2 at tile-local pixel (x, y), nested as
 // qf + x (qd + qa x + qb y) + y (qe + qc y): five FMA and no per-pixel squares.
 // The forward and backward kernels share it, so they take the same decisions.
@@ -250,7 +259,8 @@ template <int TW, int TH, int NS, int NWB>
 __device__ __forceinline__ int stage_batch(Stage<NS, NWB>& st, const uint32_t* __restrict__ vals,
                                            const ProjRec* __restrict__ proj, int64_t M, bool has,
                                            int64_t vidx, int32_t gpos, double x0c, double y0c,
-                                           double lam2) {
+                                           double lam2, StageExt<NS>* ext = nullptr,
+                                           double inv_lam = 0.0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bool keep = false;
   uint32_t m = 0;
@@ -291,6 +301,16 @@ __device__ __forceinline__ int stage_batch(Stage<NS, NWB>& st, const uint32_t* _
     st.o[k] = rec.o;
     st.pos[k] = gpos;
     st.m[k] = m;
+    if (ext) {
+      ext->B[k] = B;
+      ext->hd[k] = -u;
+      ext->he[k] = -v;
+      ext->o[k] = rec.o;
+      ext->r[k] = rec.r;
+      ext->g[k] = rec.g;
+      ext->b[k] = rec.b;
+      ext->nol[k] = -0.5 * (double)rec.o * inv_lam;
+    }
   }
   __syncthreads();
   return total;
@@ -501,6 +521,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
   static_assert(PPL >= 1 && (TW * TH) % 64 == 0 && 64 % TW == 0 && TH % (NG * PB) == 0,
                 "tile shape");
   __shared__ Stage<NS, 1> st;
+  __shared__ StageExt<NS> sx;
   __shared__ int64_t s_segbase[kMaxDepthChunks];
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   __shared__ double s_exptab[kExpTabN];
@@ -605,7 +626,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
       vidx = s_segbase[cc] + (q - s_segpre[cc]);
     }
     const int cnt = stage_batch<TW, TH, NS, 1>(st, vals, proj, M, q < hi, vidx, q, x0c, y0c,
-                                              rp.qmax);
+                                              rp.qmax, &sx, rp.inv_lam);
     // the staged positions increase with k: the entries the tile needs are
     // the first kend, those before its last contributor
     const int kend =
@@ -614,10 +635,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
       const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
       const double qd = st.qd[k], qe = st.qe[k], qf = st.qf[k];
       const int32_t pos = st.pos[k];
-      const double o = (double)st.o[k];
-      const double cr = st.r[k], cg = st.g[k], cb = st.b[k];
-      const double A = qa, B = 0.5 * qb, Cc = qc, hd = 0.5 * qd, he = 0.5 * qe;
-      const double nol = -0.5 * o * rp.inv_lam;
+      const double o = sx.o[k];
+      const double cr = sx.r[k], cg = sx.g[k], cb = sx.b[k];
+      const double A = qa, B = sx.B[k], Cc = qc, hd = sx.hd[k], he = sx.he[k];
+      const double nol = sx.nol[k];
       double gv[kGrad2d];
 #pragma unroll
       for (int f = 0; f < kGrad2d; ++f) gv[f] = 0.0;
