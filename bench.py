@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--workload", type=int, default=0,
+                    help="time another configuration instead of the 8-view benchmark: 1 (1k "
+                         "splats, 128x128), 2 (100k SH3, 1280x720), 3 (1M, 16 uneven "
+                         "cameras), 4 (3.2M, one 1920x1080 view), 5 (4 scenes, 64 cameras), "
+                         "40 (the benchmark itself)")
     ap.add_argument("--splats", type=int, default=3_200_000)
     ap.add_argument("--ags", type=int, default=1)
     ap.add_argument("--depth-chunks", type=int, default=7)
@@ -71,6 +76,17 @@ def parse():
     ap.add_argument("--no-train-stages", action="store_true",
                     help="skip the loss / Adam / densification timings")
     return ap.parse_args()
+
+
+WORKLOADS = {
+    1: "1k splats SH0, log-scale N(-3,0.5), one 128x128 view, fwd+bwd",
+    2: "100k splats SH3, log-scale N(-3,0.5), one 1280x720 view, fwd+bwd",
+    3: "1M splats SH3, 16 cameras of uneven resolution on a radius-4 sphere, fwd+bwd, batched",
+    4: "3.2M splats SH3, log-scale N(-4,1), one 1920x1080 view at z=-3, fwd+bwd",
+    5: "4 scenes (200k/500k/1M/2M splats SH3), 64 cameras at mixed resolutions, fwd+bwd, batched",
+    40: "3.2M splats SH3, log-scale N(-4,1), 8 views 1920x1080 on a radius-4 sphere, fwd+bwd, "
+        "batched",
+}
 
 
 def make_workload(n_splats, views):
@@ -101,6 +117,16 @@ def kernel_cost(name, w):
         return "hbm", 4.0 * M * 4, "B"
     if name in ("keygen", "keygen_write"):
         return "hbm", 8.0 * n + 20.0 * M, "B"
+    # depth chunks: every pair is counted and written in exactly one chunk;
+    # counting reads its position's pair id and rectangle and four
+    # summed-area-table entries and writes a count (32 B), writing reads the
+    # pair id, the rectangle and the offset (16 B) and writes 8 B per entry
+    if name == "chunk_count":
+        return "hbm", 32.0 * M, "B"
+    if name == "chunk_write":
+        return "hbm", 16.0 * M + 8.0 * n, "B"
+    if name == "zero_grad2d":
+        return "hbm", 72.0 * M, "B"
     if name == "project":
         return "hbm", float(splat_bytes) * N + 80.0 * M, "B"
     if name == "project_bwd":
@@ -395,6 +421,17 @@ def training_stages(B, S, torch, rast, sp, grads, cams, steps, warmup):
 
 
 def main():
+    if len(sys.argv) == 2 and sys.argv[1] == "--copy-calibration":
+        # a plain device-to-device copy of 1 GiB, three times: the reference
+        # against which the HBM counters (FETCH_SIZE, WRITE_SIZE) are scaled
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "copies": 3}), flush=True)
+        return
     if len(sys.argv) == 3 and sys.argv[1] == "--cpu-baseline-child":
         # the oracle baseline in a process of its own that never touches the GPU
         print(json.dumps(cpu_baseline_child(int(sys.argv[2]))), flush=True)
@@ -414,11 +451,18 @@ def main():
     from paper_2411_12440_amd import scenes as S
 
     dev = torch.device("cuda:0")
-    log(f"bench: building workload ({args.splats} splats, {args.views} views)")
-    scene, cams = make_workload(args.splats, args.views)
+    if args.workload:
+        log(f"bench: building workload {args.workload}")
+        scene, off, cams = S.workload(args.workload)
+        off = np.asarray(off, np.int64)
+        workload_name = WORKLOADS[args.workload]
+    else:
+        log(f"bench: building workload ({args.splats} splats, {args.views} views)")
+        scene, cams = make_workload(args.splats, args.views)
+        off = np.array([0, scene.n])
+        workload_name = WORKLOADS[40]
     sp = scene_to_device(scene, dev)
     G_all = torch.from_numpy(S.upstream_grad(cams, 7004)).to(dev)
-    off = np.array([0, scene.n])
     settings = dict(tile_w=16, tile_h=16, batch=args.batch, depth_chunks=args.depth_chunks)
     tuned = None
     if args.tune:
@@ -431,8 +475,8 @@ def main():
                                                   cams, 3, ags=bool(args.ags),
                                                   deterministic=bool(args.deterministic)))
         log(f"bench: tuned settings {settings}")
-    cfgkw = dict(sh_degree=3, ags=bool(args.ags), deterministic=bool(args.deterministic),
-                 **settings)
+    cfgkw = dict(sh_degree=scene.sh_degree, ags=bool(args.ags),
+                 deterministic=bool(args.deterministic), **settings)
     from paper_2411_12440_amd.autotune import effective
     eff = effective(settings)
     P = int(sum(int(w) * int(h) for w, h in zip(cams.width, cams.height)))
@@ -595,8 +639,8 @@ def main():
     # ---- roofline of the dominant kernel --------------------------------------
     T_tiles = int(rast.layout.n_tiles)
     tile_passes = max(1, ((T_tiles - 1).bit_length() + 7) // 8)
-    w = dict(N=scene.n, M=cams.n * scene.n, n_isect=n_isect, n_built=n_built, K=16, Q=Q, Qc=Qc,
-             tile_passes=tile_passes)
+    w = dict(N=scene.n, M=int(rast.layout.n_pairs), n_isect=n_isect, n_built=n_built,
+             K=(scene.sh_degree + 1) ** 2, Q=Q, Qc=Qc, tile_passes=tile_passes)
     kernels = []
     for name, launches, total in ktimes:
         row = dict(kernel=name, launches=launches, avg_ms=round(total / launches, 4),
@@ -608,6 +652,25 @@ def main():
             row["frac"] = round(rate / (HBM_PEAK_GBS * 1e9 if bound == "hbm"
                                         else FP64_VEC_PEAK_TFLOPS * 1e12), 4)
         kernels.append(row)
+    # whole pipeline: each priced kernel's floor (its algorithmic work at the
+    # chip's peak rate) summed over the step, against the measured step
+    floor_ms = priced_ms = 0.0
+    for row in kernels:
+        cost = kernel_cost(row["kernel"], w)
+        if cost is None:
+            continue
+        bound, amount, _ = cost
+        floor_ms += 1e3 * amount / (HBM_PEAK_GBS * 1e9 if bound == "hbm"
+                                    else FP64_VEC_PEAK_TFLOPS * 1e12)
+        priced_ms += row["total_ms_per_step"]
+    kernel_ms = sum(r["total_ms_per_step"] for r in kernels)
+    pipeline = dict(floor_ms=round(floor_ms, 4), step_ms=round(ms_batched, 4),
+                    frac=round(floor_ms / ms_batched, 4),
+                    priced_kernel_ms=round(priced_ms, 4),
+                    unpriced_kernel_ms=round(kernel_ms - priced_ms, 4),
+                    note="sum over the priced kernels of algorithmic work at peak (HBM 8 TB/s, "
+                         "FP64 vector 78.6 TFLOP/s) over the graph-replayed step; the unpriced "
+                         "kernels (scans, ranges, list bookkeeping) count as time with no floor")
     roof = None
     if kernels:
         dom = kernels[0]
@@ -646,8 +709,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "3.2M splats SH3, log-scale N(-4,1), 8 views 1920x1080 on a "
-                               "radius-4 sphere, fwd+bwd, batched",
+        "config": {"workload": workload_name,
                    "views": cams.n, "pixels_per_step": P, "n_isect": n_isect,
                    "entries_built": n_built, "depth_chunks": settings["depth_chunks"],
                    "chunk_entries": chunk_entries,
@@ -666,7 +728,8 @@ def main():
         "kernel_family": family,
         "training_stages": train,
         "roofline": roof,
-        "kernels": kernels[:12],
+        "pipeline": pipeline,
+        "kernels": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
