@@ -165,7 +165,10 @@ def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5
     # splat gradients end to end, normwise.  Stage (2) separates the rounding
     # of the FP32 per-pixel terms, which the chain through the projection can
     # amplify where the centre and conic terms of a large splat cancel, from
-    # the projection backward itself.
+    # the projection backward itself.  The end-to-end difference is exactly
+    # stage (1)'s difference carried through that (linear) chain, so stages
+    # (1) and (2) are the element-by-element bars and (3) is normwise; its
+    # worst element ratio is still printed.
     if graph:
         dimg = torch.from_numpy(G).cuda()
         grads = {kk: torch.empty_like(v) for kk, v in sp.items()}
@@ -241,7 +244,7 @@ def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5
     for k, v in mine3.items():
         assert np.all(v[~touched] == 0.0), k
         assert_close(f"d_{k} (staged)", v[touched], staged[k][touched])
-        assert_close(f"d_{k}", v[touched], want[k][touched])
+        assert_close(f"d_{k}", v[touched], want[k][touched], elementwise=False)
 
 
 def test_benchmark_configuration_sampled():
