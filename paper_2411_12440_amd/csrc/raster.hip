@@ -107,19 +107,16 @@ struct PairEval {
 };
 
 // sqrt(q) for q >= 0 (a negative q, possible only by rounding of the
-// expanded quadratic form at a splat's centre, counts as 0): the FP32
-// reciprocal square root as a start and one FP64 Newton step, which brings
-// the relative error from about 2^-22 to below 1e-13.  Below 1e-30 the result
-// is 0 (an absolute error under 1e-15).
-// The same start gives 1/sqrt(q) with one Newton step for the reciprocal
-// square root.
+// expanded quadratic form at a splat's centre, counts as 0), with 1/sqrt(q)
+// in *inv: the FP32 reciprocal square root as a start and one FP64 Newton
+// step for the reciprocal square root bring the relative error of 1/sqrt(q)
+// from about 2^-22 to below 1e-13, and sqrt(q) = q / sqrt(q) keeps it.  Below
+// 1e-30 both are 0 (an absolute error under 1e-15, and no slope at the apex).
 __device__ __forceinline__ double sqrt_nonneg(double q, double* inv) {
   const double y = (double)__builtin_amdgcn_rsqf((float)q);
-  const bool pos = q > 1e-30;
-  *inv = pos ? y * fma(-0.5 * q, y * y, 1.5) : 0.0;   // no slope at the apex
-  if (!pos) return 0.0;
-  const double d0 = q * y;
-  return fma(0.5 * y, fma(-d0, d0, q), d0);
+  const double r = y * fma(-0.5 * q, y * y, 1.5);
+  *inv = q > 1e-30 ? r : 0.0;
+  return q * *inv;
 }
 
 // Kernels of the family (LS_KERNEL_*), a template parameter of the raster
@@ -129,6 +126,20 @@ __device__ __forceinline__ double sqrt_nonneg(double q, double* inv) {
 template <int KF>
 constexpr bool kernel_uses_exp() {
   return KF == LS_KERNEL_GAUSSIAN || KF == LS_KERNEL_LAPLACIAN;
+}
+
+// min and max of two doubles that are not NaN, as single instructions: with
+// fmin and fmax the compiler canonicalises a bound that is carried in a
+// register at every use.
+__device__ __forceinline__ double min_nn(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double max_nn(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
 template <int KF>
@@ -170,10 +181,10 @@ __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterPa
     e.alpha = o * e.f;
     e.oma = 1.0 - e.alpha;
   }
-  const bool clamped = e.alpha > rp.amax;
-  e.alpha = fmin(e.alpha, rp.amax);
-  e.oma = clamped ? rp.oma_max : e.oma;
-  e.nc = clamped ? 0.0 : 1.0;
+  // the clamp: alpha at most alpha_max, 1 - alpha at least 1 - alpha_max
+  e.nc = e.alpha > rp.amax ? 0.0 : 1.0;
+  e.alpha = min_nn(e.alpha, rp.amax);
+  e.oma = max_nn(e.oma, rp.oma_max);
   return e;
 }
 
@@ -201,11 +212,13 @@ __device__ __forceinline__ int cam_of_tile(const CamInfo* cams, int C, int64_t t
 // pixel-centre rectangle are dropped and the survivors compacted in list
 // order, so the per-pixel loop only sees splats that can touch the tile.
 // NS staged entries at most; NW waves in the block
-template <int NS, int NW>
+// The FP32 colour and opacity are staged for the forward pass (RGBO); the
+// backward pass stages them widened in StageExt instead.
+template <int NS, int NW, bool RGBO = true>
 struct Stage {
   // D'^2 at tile-local pixel (x, y) = qa x^2 + qb xy + qc y^2 + qd x + qe y + qf
   double qa[NS], qb[NS], qc[NS], qd[NS], qe[NS], qf[NS];
-  float r[NS], g[NS], b[NS], o[NS];
+  float r[RGBO ? NS : 1], g[RGBO ? NS : 1], b[RGBO ? NS : 1], o[RGBO ? NS : 1];
   int32_t pos[NS];           // position in the tile list
   uint32_t m[NS];            // pair id
   int32_t wcount[NW];
@@ -215,17 +228,25 @@ struct Stage {
 // quadratic form so that the entry loop does not recompute them per entry.
 template <int NS>
 struct StageExt {
-  double B[NS], hd[NS], he[NS];           // conic B; (qd, qe) / 2 = -(u, v) at the tile origin
   double o[NS], r[NS], g[NS], b[NS];      // opacity and colour, widened
   double nol[NS];                         // -o / (2 lambda)
 };
 
 // D'^2 at tile-local pixel (x, y), nested as
-// qf + x (qd + qa x + qb y) + y (qe + qc y): five FMA and no per-pixel squares.
-// The forward and backward kernels share it, so they take the same decisions.
-__device__ __forceinline__ double quad_local(double qa, double qb, double qc, double qd, double qe,
-                                             double qf, double x, double y) {
-  return fma(x, fma(qa, x, fma(qb, y, qd)), fma(y, fma(qc, y, qe), qf));
+// (qf + x (qd + qa x)) + y ((qe + qb x) + qc y): five FMA and no per-pixel
+// squares.  The two x-only terms are shared by the pixels of a column, so a
+// thread that holds several pixels of one column pays two FMA per pixel.  The
+// forward and backward kernels evaluate it in this order, so they take the
+// same decisions.
+struct QuadX {
+  double P, R;   // qf + x (qd + qa x) and qe + qb x
+};
+__device__ __forceinline__ QuadX quad_x(double qa, double qb, double qd, double qe, double qf,
+                                        double x) {
+  return QuadX{fma(x, fma(qa, x, qd), qf), fma(qb, x, qe)};
+}
+__device__ __forceinline__ double quad_y(const QuadX& h, double qc, double y) {
+  return fma(y, fma(qc, y, h.R), h.P);
 }
 
 // true if min over [0, w] x [0, h] of A dx^2 + 2B dx dy + C dy^2 (dx = x - ox,
@@ -255,8 +276,8 @@ __device__ __forceinline__ bool ellipse_hits_rect(double ox, double oy, double A
 // Stage one batch: thread i (i < NT) brings entry `vidx` of the sorted
 // values (if `has`), whose position in the tile's list is `gpos`.  Returns the
 // number of surviving entries (block-uniform).
-template <int TW, int TH, int NS, int NWB>
-__device__ __forceinline__ int stage_batch(Stage<NS, NWB>& st, const uint32_t* __restrict__ vals,
+template <int TW, int TH, int NS, int NWB, bool RGBO>
+__device__ __forceinline__ int stage_batch(Stage<NS, NWB, RGBO>& st, const uint32_t* __restrict__ vals,
                                            const ProjRec* __restrict__ proj, int64_t M, bool has,
                                            int64_t vidx, int32_t gpos, double x0c, double y0c,
                                            double lam2, StageExt<NS>* ext = nullptr,
@@ -295,16 +316,15 @@ __device__ __forceinline__ int stage_batch(Stage<NS, NWB>& st, const uint32_t* _
     st.qd[k] = -2.0 * u;
     st.qe[k] = -2.0 * v;
     st.qf[k] = ox * u + oy * v;
-    st.r[k] = rec.r;
-    st.g[k] = rec.g;
-    st.b[k] = rec.b;
-    st.o[k] = rec.o;
+    if constexpr (RGBO) {
+      st.r[k] = rec.r;
+      st.g[k] = rec.g;
+      st.b[k] = rec.b;
+      st.o[k] = rec.o;
+    }
     st.pos[k] = gpos;
     st.m[k] = m;
     if (ext) {
-      ext->B[k] = B;
-      ext->hd[k] = -u;
-      ext->he[k] = -v;
       ext->o[k] = rec.o;
       ext->r[k] = rec.r;
       ext->g[k] = rec.g;
@@ -418,12 +438,12 @@ void raster_fwd_kernel(
                                                   prefix + p0 + tid, x0c, y0c, rp.qmax);
     if (!all_done()) {
       for (int k = 0; k < cnt; ++k) {
-        const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
-        const double qd = st.qd[k], qe = st.qe[k], qf = st.qf[k];
+        const QuadX hx = quad_x(st.qa[k], st.qb[k], st.qd[k], st.qe[k], st.qf[k], lx);
+        const double qc = st.qc[k];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
           if (done[j]) continue;
-          const double q = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
+          const double q = quad_y(hx, qc, ly[j]);
           if (!(q < rp.qmax)) continue;
           const PairEval e = pair_eval<KF>(q, (double)st.o[k], rp, s_exptab);
           if (!(e.alpha >= rp.amin_pos)) continue;
@@ -495,6 +515,45 @@ constexpr bool ags_table() { return AG == kAgsTabGeo || AG == kAgsTabWhole; }
 template <int AG>
 constexpr bool ags_whole() { return AG == kAgsTabWhole || AG == kAgsSeriesWhole; }
 
+// Wave-wide sums of nine FP64 values per lane, through LDS, for a block of
+// one wave.  Every lane stores its nine values; field f of lane 8p + q sits at
+// f * 80 + 10 p + q (doubles).  Lane l = 8f + p (f < 8) then adds the eight
+// values of field f in part p, and every lane the eight of field 8 in part p;
+// lanes 0..7 store the latter and all lanes the former, and lane f (f < 9)
+// adds the eight partial sums of field f (stored at 10 f + p).  The padding
+// (parts of 10, fields of 80) spreads each 16-byte read of eight lanes over
+// distinct banks.  Lanes
+// 0..8 return the sums of fields 0..8 (the other lanes a copy of field 8's).
+// Within one wave the LDS accesses execute in program order; the fences keep
+// the compiler from moving one lane's store across another lane's load.
+constexpr int kRedField = 80;
+constexpr int kRedDoubles = 9 * kRedField;
+__device__ __forceinline__ double wave_sum9_lds(const double (&v)[9], double* red, int lane) {
+  const int f = lane >> 3, p = lane & 7;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  double* w = red + 10 * (lane >> 3) + (lane & 7);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) w[i * kRedField] = v[i];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const double2* a = reinterpret_cast<const double2*>(red + f * kRedField + 10 * p);
+  const double2* b = reinterpret_cast<const double2*>(red + 8 * kRedField + 10 * p);
+  double x = a[0].x + a[0].y, y = b[0].x + b[0].y;
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    x += a[j].x + a[j].y;
+    y += b[j].x + b[j].y;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  red[10 * f + p] = x;
+  if (lane < 8) red[80 + p] = y;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const double2* c = reinterpret_cast<const double2*>(red + 10 * (lane < 9 ? lane : 8));
+  double z = c[0].x + c[0].y;
+#pragma unroll
+  for (int j = 1; j < 4; ++j) z += c[j].x + c[j].y;
+  return z;
+}
+
 // Backward kernel: one wave per tile, TW * TH / 64 pixels per lane.  Lane l
 // owns column l % TW; its pixels come in groups of (up to) two vertically
 // adjacent ones, one group per horizontal band of the tile (a 16x16 tile:
@@ -520,8 +579,9 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
   constexpr int NS = 64;                  // staged entries per batch, one per lane
   static_assert(PPL >= 1 && (TW * TH) % 64 == 0 && 64 % TW == 0 && TH % (NG * PB) == 0,
                 "tile shape");
-  __shared__ Stage<NS, 1> st;
+  __shared__ Stage<NS, 1, false> st;
   __shared__ StageExt<NS> sx;
+  __shared__ __align__(16) double s_red[kRedDoubles];
   __shared__ int64_t s_segbase[kMaxDepthChunks];
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   __shared__ double s_exptab[kExpTabN];
@@ -598,21 +658,16 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
       const int32_t y = __shfl_xor(glast[g], d, 64);
       glast[g] = y > glast[g] ? y : glast[g];
     }
+    glast[g] = __builtin_amdgcn_readfirstlane(glast[g]);
   }
   int32_t tile_last = 0;
 #pragma unroll
   for (int g = 0; g < NG; ++g) tile_last = glast[g] > tile_last ? glast[g] : tile_last;
-  // factor of the wave sum that lane 8g holds (field wave_sum8_field(g)):
-  // the centre terms and the off-diagonal covariance term were summed
-  // without their -2, the diagonal covariance terms without their -1
-  double fac;
-  {
-    const int f = wave_sum8_field((lane >> 3) & 7);
-    fac = (f == 2 || f == 4) ? -1.0 : (f < 5 ? -2.0 : 1.0);
-  }
-  const bool top = lane == 63;
-  const int my_field = top ? 8 : wave_sum8_field(lane >> 3);
-  const bool holder = (lane & 7) == 0 || top;   // lanes that end with a field's sum
+  // factor of the wave sum of field `lane` (lanes 0..8): the geometric
+  // terms are summed with U = 2u in place of u and without their sign, so
+  // the centre terms take -1, the diagonal covariance terms -1/4 and the
+  // off-diagonal one -1/2 (powers of two: exact)
+  const double fac = lane < 2 ? -1.0 : lane == 3 ? -0.5 : lane < 5 ? -0.25 : 1.0;
 
   const int bsz = batch < NS ? batch : NS;
   for (int32_t hi = tile_last; hi > 0; hi -= bsz) {
@@ -632,12 +687,18 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
     const int kend =
         __popcll(__builtin_amdgcn_ballot_w64(lane < cnt && st.pos[lane] < tile_last));
     for (int k = kend - 1; k >= 0; --k) {
-      const double qa = st.qa[k], qb = st.qb[k], qc = st.qc[k];
-      const double qd = st.qd[k], qe = st.qe[k], qf = st.qf[k];
-      const int32_t pos = st.pos[k];
+      // the entry is the same for every lane: its position in the list is
+      // read into a scalar register, so the band tests branch uniformly
+      const int32_t pos = __builtin_amdgcn_readfirstlane(st.pos[k]);
+      const double qc = st.qc[k];
+      const QuadX hx = quad_x(st.qa[k], st.qb[k], st.qd[k], st.qe[k], st.qf[k], lx);
       const double o = sx.o[k];
       const double cr = sx.r[k], cg = sx.g[k], cb = sx.b[k];
-      const double A = qa, B = sx.B[k], Cc = qc, hd = sx.hd[k], he = sx.he[k];
+      // U = 2 cov^-1 (x - centre), the gradient of D'^2 in x:
+      // (2 qa x + qb y + qd, qb x + 2 qc y + qe); its x-only parts are shared
+      // by the lane's pixels (the second is quad_x's R)
+      const double qb = st.qb[k], qc2 = 2.0 * qc;
+      const double Ux0 = fma(2.0 * st.qa[k], lx, st.qd[k]), Uy0 = hx.R;
       const double nol = sx.nol[k];
       double gv[kGrad2d];
 #pragma unroll
@@ -655,7 +716,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
           const int j = g * PB + i;
-          qq[i] = quad_local(qa, qb, qc, qd, qe, qf, lx, ly[j]);
+          qq[i] = quad_y(hx, qc, ly[j]);
           e[i] = pair_eval<KF>(qq[i], o, rp, s_exptab);
           contrib[i] = pos < mylast[j] && qq[i] < rp.qmax && e[i].alpha >= rp.amin_pos;
           any = any || contrib[i];
@@ -688,8 +749,8 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
           // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the
           // conic) is what the projection backward differentiates, so its
           // gradient is summed here; going through the inverse after the sum
-          // would amplify the sum's rounding for elongated splats.  The
-          // factors -2 and -1 are applied to the wave sums.
+          // would amplify the sum's rounding for elongated splats.  The sums
+          // take U = 2u; the factors are applied to the wave sums.
           // dL/dq = dL/dalpha o f'(q): linear -omega / (2 lambda D); Gaussian
           // -f / (2 lambda^2); quadratic -1 / lambda^2; Laplacian
           // -f / (2 lambda D); raised cosine -pi sin(pi D/lambda) / (4 lambda D)
@@ -704,15 +765,14 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
             gq = -0.5 * (dLda * e[i].alpha) * (rp.inv_lam * e[i].nc) * e[i].invD;
           else
             gq = -0.7853981633974483 * (o * dLda) * (rp.inv_lam * e[i].nc) * e[i].sx * e[i].invD;
-          // u = cov^-1 (x - centre) = (A x + B y, B x + C y) - (qd, qe) / -2
-          const double ux = fma(A, lx, fma(B, ly[j], hd));
-          const double uy = fma(B, lx, fma(Cc, ly[j], he));
-          const double gux = gq * ux, guy = gq * uy;
-          gv[0] += gux;                    // x -2
-          gv[1] += guy;                    // x -2
-          gv[2] = fma(gux, ux, gv[2]);     // x -1
-          gv[3] = fma(gux, uy, gv[3]);     // x -2
-          gv[4] = fma(guy, uy, gv[4]);     // x -1
+          const double Ux = fma(qb, ly[j], Ux0);
+          const double Uy = fma(qc2, ly[j], Uy0);
+          const double gux = gq * Ux, guy = gq * Uy;
+          gv[0] += gux;                    // x -1
+          gv[1] += guy;                    // x -1
+          gv[2] = fma(gux, Ux, gv[2]);     // x -1/4
+          gv[3] = fma(gux, Uy, gv[3]);     // x -1/2
+          gv[4] = fma(guy, Uy, gv[4]);     // x -1/4
           // opacity and colour: scaled by omega only under the whole-pair scope
           const double go = ags_whole<AG>() ? dLda * e[i].nc * om : dLda * e[i].nc;
           gv[5] = fma(e[i].f, go, gv[5]);
@@ -723,21 +783,19 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
         }
       }
       if (!used) continue;
-      // wave-wide FP64 sums (all lanes active here): lanes 8g hold fields
-      // 0..7 (times their factor), lane 63 field 8
-      static_assert(kGrad2d == 9, "eight fields summed together, one alone");
-      const double s8 = wave_sum8_d(gv, lane) * fac;
-      const double s1 = wave_sum_all_d(gv[8]);
-      const double sv = top ? s1 : s8;
+      // wave-wide FP64 sums (all lanes active here): lane f < 9 holds
+      // field f times its factor
+      static_assert(kGrad2d == 9, "nine fields");
+      const double sv = wave_sum9_lds(gv, s_red, lane) * fac;
       if (partial) {
         // deterministic mode: the tile's sums of this entry go to the
         // entry's slot in pair order; the pair sums are formed afterwards
         int cc = 0;
         while (cc + 1 < K && s_segpre[cc + 1] <= pos) ++cc;
         const int64_t ent = s_segbase[cc] + (pos - s_segpre[cc]);
-        if (holder) partial[(int64_t)det_slot[ent] * kGrad2d + my_field] = sv;
-      } else if (holder && sv != 0.0) {
-        unsafeAtomicAdd(grad2d + (int64_t)my_field * M + (int64_t)st.m[k], sv);
+        if (lane < kGrad2d) partial[(int64_t)det_slot[ent] * kGrad2d + lane] = sv;
+      } else if (lane < kGrad2d && sv != 0.0) {
+        unsafeAtomicAdd(grad2d + (int64_t)lane * M + (int64_t)st.m[k], sv);
       }
     }
   }
