@@ -188,10 +188,21 @@ __device__ __forceinline__ PairEval pair_eval(double q, double o, const RasterPa
   return e;
 }
 
+// Tile of block b of nb.  Blocks are dealt to the 8 XCDs round-robin
+// (b mod 8), each with its own L2.  Tiles are taken in strips of 64
+// consecutive tiles (a run along a tile row), and XCD x works through strips
+// x, x + 8, x + 16, ... in order, so each XCD's blocks share the splats of
+// their strip while every view's work is spread over all eight XCDs.  (With
+// one contiguous eighth of the tiles per XCD, eight views put one view on
+// each XCD, and after the first depth chunk the XCD of the busiest view was
+// left running alone.)  Blocks past the last whole group of 8 strips map to
+// themselves.
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  constexpr int64_t G = 64;
+  const int64_t full = nb / (8 * G) * (8 * G);
+  if (b >= full) return b;
   const int64_t x = b & 7, k = b >> 3;
-  const int64_t q = nb >> 3, r = nb & 7;
-  return x * q + (x < r ? x : r) + k;
+  return ((k / G) * 8 + x) * G + k % G;
 }
 
 __device__ __forceinline__ int cam_of_tile(const CamInfo* cams, int C, int64_t t) {
