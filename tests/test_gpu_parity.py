@@ -345,6 +345,50 @@ def test_autograd_stale_forward_raises():
     assert all(l.grad is not None and torch.isfinite(l.grad).all() for l in leaves2)
 
 
+@pytest.mark.parametrize("chunks", [1, 7])
+def test_backward_sums_start_at_zero(chunks):
+    """Every backward pass starts its per-pair sums from zero: three backward
+    passes after one forward, and one after a second forward, give the same
+    per-pair sums (up to the order of the FP64 atomics) and the oracle's
+    gradients; a backward with a different upstream gradient in between
+    gives its own sums and changes nothing for the ones after it."""
+    import torch
+    say(f"case: repeated backward passes after one forward, depth chunks {chunks}")
+    scs = [scenes.make_scene(n, 930 + i, -3.0, 0.5, 1) for i, n in enumerate((900, 500))]
+    scene, off = scenes.concat_scenes(scs)
+    cams = scenes.sphere_cameras(3, 4.0, [(96, 80), (150, 70), (64, 64)], scene_of_cam=[0, 1, 0])
+    ocfg, gkw = cfg_pair(depth_chunks=chunks, ags=True)
+    G = scenes.upstream_grad(cams, 7021)
+    fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
+    G = (G * ~pixel_flags_to_image(fw.flag, cams)).astype(np.float32)
+    rast, sp = gpu_forward(scene, off, cams, gkw)
+    Gd = torch.from_numpy(G).cuda()
+    M = int(rast.layout.n_pairs)
+
+    def sums():
+        torch.cuda.synchronize()
+        return rast.view("grad2d", torch.float64, 9 * M).cpu().numpy().reshape(9, M).copy()
+
+    first = _grads_to_numpy(rast.backward(sp, Gd))
+    ref = sums()
+    scale = np.abs(ref).max()
+    assert scale > 0
+    for rep in range(2):
+        rast.backward(sp, Gd)
+        assert np.abs(sums() - ref).max() <= 1e-12 * scale, rep
+    # a different upstream gradient (twice the first: exact in FP32, and every
+    # FP64 term of the sums scales by 2 exactly)
+    rast.backward(sp, 2.0 * Gd)
+    assert np.abs(sums() - 2.0 * ref).max() <= 2e-12 * scale
+    rast.forward(sp)
+    torch.cuda.synchronize()
+    last = _grads_to_numpy(rast.backward(sp, Gd))
+    assert np.abs(sums() - ref).max() <= 1e-12 * scale
+    go = render_backward(fw, scene, cams, G)
+    compare_grads(first, go, scene)
+    compare_grads(last, go, scene)
+
+
 @pytest.mark.parametrize("chunks", [1, 3])
 def test_deterministic_backward(chunks):
     """Deterministic mode: two backward passes give bitwise-equal splat
