@@ -41,7 +41,6 @@ struct RasterParams {
   double amin_pos;    // a pair is used iff alpha >= amin_pos: alpha > 0 and alpha >= amin
   float bg0, bg1, bg2;
   int ags, ags_arg, ags_scope;
-  int exp_tab;        // the AGS weight of every contributing pair can use exp_neg_tab
   double ags_scale;   // AGS exponent per unit D'^2: 1 / lambda^2 or 1
   double qmax;        // extent^2: a pair is kept while D'^2 < qmax (the support)
   double ghalf;       // 1 / (2 lambda^2), the Gaussian's exponent per unit D'^2
@@ -516,15 +515,23 @@ void raster_fwd_kernel(
 }
 
 // Adaptive gradient scaling in the backward kernel, a template parameter:
-// off; or the weight from the LDS table (exp_neg_tab, every contributing
-// pair's exponent in its range) or from the series (exp_neg), each with
-// omega applied to the geometric gradient only or to every gradient of the
-// pair.
-enum { kAgsOff = 0, kAgsTabGeo = 1, kAgsTabWhole = 2, kAgsSeriesGeo = 3, kAgsSeriesWhole = 4 };
+// off, or omega applied to the geometric gradient only or to every gradient
+// of the pair.
+enum { kAgsOff = 0, kAgsGeo = 1, kAgsWhole = 2 };
 template <int AG>
-constexpr bool ags_table() { return AG == kAgsTabGeo || AG == kAgsTabWhole; }
-template <int AG>
-constexpr bool ags_whole() { return AG == kAgsTabWhole || AG == kAgsSeriesWhole; }
+constexpr bool ags_whole() { return AG == kAgsWhole; }
+
+// The AGS weight omega = e^-x, x >= 0, in FP32 precision: the hardware base-2
+// exponential of -x log2(e) formed in FP32.  The FP32 rounding of x and of
+// the product puts the relative error below 5e-7 for x < 8 (the D'^2 reading
+// with lambda 2.5 reaches 6.25 at the support's edge) and below 1e-6 for
+// x < 16; far out, where omega is below 1e-7, it grows with x, and below
+// 2^-126 the weight is 0.  omega only scales a gradient direction, so this
+// precision is far inside the gradients' 1e-5 tolerance; every other
+// per-pixel term stays FP64.
+__device__ __forceinline__ double ags_weight(double x) {
+  return (double)__builtin_amdgcn_exp2f((float)x * -1.44269504088896341f);
+}
 
 // Wave-wide sums of nine FP64 values per lane, through LDS, for a block of
 // one wave.  Every lane stores its nine values; field f of lane 8p + q sits at
@@ -597,7 +604,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
   __shared__ int32_t s_segpre[kMaxDepthChunks + 1];
   __shared__ double s_exptab[kExpTabN];
   const int lane = threadIdx.x;
-  if (kernel_uses_exp<KF>() || ags_table<AG>())
+  if (kernel_uses_exp<KF>())
     for (int i = lane; i < kExpTabN; i += 64) s_exptab[i] = exp_neg((double)i / kExpTabStep);
   const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int c = cam_of_tile(cams, C, tile);
@@ -754,7 +761,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(
           double om = 1.0;
           if constexpr (AG != kAgsOff) {
             const double xa = qq[i] * rp.ags_scale;
-            om = ags_table<AG>() ? exp_neg_tab(xa, s_exptab) : exp_neg(xa);
+            om = ags_weight(xa);
           }
           // q = d^T cov^-1 d with d = pixel - centre and u = cov^-1 d:
           // dq/dcentre = -2 u, dq/dcov = -u u^T.  The covariance (not the
@@ -844,9 +851,6 @@ RasterParams make_params(const ls_config* cfg) {
   rp.ags = cfg->ags;
   rp.ags_arg = cfg->ags_arg;
   rp.ags_scope = cfg->ags_scope;
-  // largest AGS exponent of a contributing pair (q < lambda^2)
-  const double xmax = cfg->ags_arg ? 1.0 : rp.lam2;
-  rp.exp_tab = xmax < (double)kExpTabN / kExpTabStep - 0.01;
   rp.ags_scale = cfg->ags_arg ? rp.inv_lam2 : 1.0;
   return rp;
 }
@@ -941,9 +945,7 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     dim3 grid((unsigned)p.T);
     ProfScope ps("raster_bwd", s);
     // AGS is defined for the linear kernel only (checked by the entry point)
-    const int ag = !cfg->ags ? kAgsOff
-                   : rp.exp_tab ? (cfg->ags_scope ? kAgsTabWhole : kAgsTabGeo)
-                                : (cfg->ags_scope ? kAgsSeriesWhole : kAgsSeriesGeo);
+    const int ag = !cfg->ags ? kAgsOff : cfg->ags_scope ? kAgsWhole : kAgsGeo;
 #define LS_BWD(TW_, TH_, KF_, AG_)                                                                 \
   hipLaunchKernelGGL((raster_bwd_kernel<TW_, TH_, KF_, AG_>), grid, dim3(64), 0, s,                \
                      cams, p.C, ranges, p.T, p.K, chunk_base, vals, proj, p.M, batch, rp,      \
@@ -956,10 +958,8 @@ hipError_t launch_raster_bwd(const Plan& p, const ls_config* cfg, const ls_splat
     case LS_KERNEL_QUADRATIC: LS_BWD(TW_, TH_, LS_KERNEL_QUADRATIC, kAgsOff); break;               \
     default:                                                                                       \
       switch (ag) {                                                                                \
-        case kAgsTabGeo: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsTabGeo); break;                    \
-        case kAgsTabWhole: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsTabWhole); break;                \
-        case kAgsSeriesGeo: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsSeriesGeo); break;              \
-        case kAgsSeriesWhole: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsSeriesWhole); break;          \
+        case kAgsGeo: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsGeo); break;                          \
+        case kAgsWhole: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsWhole); break;                      \
         default: LS_BWD(TW_, TH_, LS_KERNEL_LINEAR, kAgsOff); break;                               \
       }                                                                                            \
       break;                                                                                       \
