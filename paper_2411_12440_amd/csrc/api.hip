@@ -186,6 +186,9 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   p->chunk_spans = take(8 * K);
   p->alive = take(4 * T);
   p->sat = take(4 * T);
+  // depth chunks: the alive flags one bit per tile (global tile id order,
+  // two zero words past the end)
+  p->abits = take(4 * (p->K > 1 ? 2 * ((T + 63) / 64) + 2 : 1));
   p->drect = take(8 * M);
   if (p->K > 1) {
     p->state = take(32 * (size_t)p->P);

@@ -637,6 +637,32 @@ __global__ __launch_bounds__(256) void alive_sat_cols(const CamInfo* __restrict_
   }
 }
 
+// The alive flags one bit per tile, in global tile id order (bit t & 31 of
+// word t >> 5), one wave per 64 tiles; the grid has one more wave, which
+// writes the two zero words past the end.
+__global__ __launch_bounds__(256) void alive_bits_kernel(const uint32_t* __restrict__ alive,
+                                                         int64_t T, int64_t nwaves,
+                                                         uint32_t* __restrict__ abits) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nwaves) return;
+  const int64_t t = w * 64 + lane;
+  const uint64_t b = __builtin_amdgcn_ballot_w64(t < T && alive[t] != 0u);
+  if (lane == 0) {
+    abits[2 * w] = (uint32_t)b;
+    abits[2 * w + 1] = (uint32_t)(b >> 32);
+  }
+}
+
+// alive bits of the n <= 32 tiles t, t + 1, ... (bit i: tile t + i)
+__device__ __forceinline__ uint32_t alive_run(const uint32_t* __restrict__ abits, uint32_t t,
+                                              uint32_t n) {
+  const uint32_t i = t >> 5;
+  const uint64_t v = ((uint64_t)abits[i + 1] << 32) | abits[i];
+  const uint32_t x = (uint32_t)(v >> (t & 31u));
+  return n >= 32u ? x : x & ((1u << n) - 1u);
+}
+
 __device__ __forceinline__ uint32_t sat_query(const uint32_t* S, int GX, int x0, int y0, int x1,
                                               int y1) {
   auto at = [&](int x, int y) -> uint32_t {
@@ -649,14 +675,14 @@ __device__ __forceinline__ uint32_t sat_query(const uint32_t* S, int GX, int x0,
 // number of alive tiles in its rectangle (from the summed-area table), and a
 // mask that tells the writer where they are: all ones when every tile is
 // alive; for a partly alive rectangle of at most kSmallRect tiles, bit j is
-// tile j (row-major) of the rectangle; 0 for a larger partly alive one (a
-// wave of the second write kernel scans it) or an empty count.
+// tile j (row-major) of the rectangle; 0 for a larger partly alive one (the
+// second write kernel writes it) or an empty count.
 constexpr int kSmallRect = 32;
 
 __global__ __launch_bounds__(256) void chunk_count_kernel(
     const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
     const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
-    const uint32_t* __restrict__ sat, const uint32_t* __restrict__ alive,
+    const uint32_t* __restrict__ sat, const uint32_t* __restrict__ abits,
     const int32_t* __restrict__ flags, uint32_t* __restrict__ pcnt,
     uint32_t* __restrict__ pmask) {
   const int64_t p = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -672,12 +698,9 @@ __global__ __launch_bounds__(256) void chunk_count_kernel(
     if (k == area) {
       mask = 0xFFFFFFFFu;                  // every tile alive
     } else if (k != 0 && area <= (uint32_t)kSmallRect) {
-      int j = 0;
-      for (int ty = r.y; ty <= r.w; ++ty) {
-        const uint32_t* row = alive + ci.tile_off + (int64_t)ty * ci.GX;
-        for (int tx = r.x; tx <= r.z; ++tx, ++j)
-          if (row[tx]) mask |= 1u << j;
-      }
+      const uint32_t w = (uint32_t)(r.z - r.x + 1);
+      uint32_t t = (uint32_t)(ci.tile_off + (int64_t)r.y * ci.GX + r.x);
+      for (uint32_t j = 0; j < area; j += w, t += (uint32_t)ci.GX) mask |= alive_run(abits, t, w) << j;
     }
   }
   pcnt[p - lo] = k;
@@ -813,55 +836,109 @@ __global__ __launch_bounds__(256) void chunk_write_span_kernel(
   }
 }
 
-// The large, partly alive rectangles of the chunk: queued per block, each
-// written by one wave, 64 tiles of the rectangle (row-major) per step with
-// ballot compaction.
+// The large, partly alive rectangles of the chunk.  A block collects those of
+// its 256 pairs, and each wave takes up to 64 of them.  The wave cuts their
+// rows into units of up to 32 tiles (one word of the alive bits each),
+// numbered rectangle after rectangle, and walks the units 64 at a time: each
+// lane finds its unit's rectangle, reads the unit's alive bits and writes one
+// entry per set bit.  A wave-wide scan of the bit counts numbers the entries
+// of the wave's rectangles one after another (each rectangle's count is its
+// number of alive tiles), which places every entry in its rectangle's range
+// in row-major tile order.
 __global__ __launch_bounds__(256) void chunk_write_big_kernel(
     const uint32_t* __restrict__ order, const ushort4* __restrict__ drect,
     const CamInfo* __restrict__ cams, int C, int64_t M, int64_t lo, int64_t hi,
-    const uint32_t* __restrict__ alive, const uint32_t* __restrict__ pcnt,
+    const uint32_t* __restrict__ abits, const uint32_t* __restrict__ pcnt,
     const uint32_t* __restrict__ poff, const uint32_t* __restrict__ pmask,
     const int64_t* __restrict__ chunk_base, const int64_t* __restrict__ chunk_n,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ int64_t s_big[256];
+  __shared__ uint32_t s_big[256];
   __shared__ int s_nbig;
+  __shared__ uint32_t s_ustart[4][65];
+  __shared__ uint32_t s_row0[4][64], s_gx[4][64], s_w[4][64], s_nseg[4][64], s_m[4][64];
+  __shared__ int64_t s_dst[4][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (*chunk_n == 0) return;
   if (tid == 0) s_nbig = 0;
   __syncthreads();
-  const int64_t p = lo + (int64_t)blockIdx.x * 256 + tid;
-  if (p < hi && pcnt[p - lo] > 0 && pmask[p - lo] == 0u) s_big[atomicAdd(&s_nbig, 1)] = p;
+  const int64_t p0 = lo + (int64_t)blockIdx.x * 256 + tid;
+  if (p0 < hi && pcnt[p0 - lo] > 0 && pmask[p0 - lo] == 0u)
+    s_big[atomicAdd(&s_nbig, 1)] = (uint32_t)p0;
   __syncthreads();
   const int nbig = s_nbig;
   const int64_t base = *chunk_base;
-  for (int b = wave; b < nbig; b += 4) {
-    const int64_t q = s_big[b];
-    uint32_t m = order[q];
-    if (m >= (uint64_t)M) m = 0;
-    const ushort4 r = drect[q];
-    const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
-    const uint32_t w = (uint32_t)(r.z - r.x + 1);
-    const uint32_t area = w * (uint32_t)(r.w - r.y + 1);
-    const int64_t row0 = ci.tile_off + (int64_t)r.y * ci.GX + r.x;
-    int64_t dst = base + poff[q - lo];
-    for (uint32_t i0 = 0; i0 < area; i0 += 64) {
-      const uint32_t i = i0 + (uint32_t)lane;
-      bool keep = false;
-      uint32_t tile = 0;
-      if (i < area) {
-        uint32_t tx;
-        const uint32_t ty = div_small(i, w, &tx);
-        tile = (uint32_t)(row0 + (int64_t)ty * ci.GX + tx);
-        keep = alive[tile] != 0u;
+  {
+    const int b = wave * 64 + lane;
+    if (wave * 64 >= nbig) return;
+    uint32_t units = 0, k = 0;
+    int64_t dst = 0;
+    if (b < nbig) {
+      const uint32_t q = s_big[b];
+      uint32_t m = order[q];
+      if (m >= (uint64_t)M) m = 0;
+      const ushort4 r = drect[q];
+      const CamInfo& ci = cams[cam_of_pair(cams, C, (int64_t)m)];
+      const uint32_t w = (uint32_t)(r.z - r.x + 1), h = (uint32_t)(r.w - r.y + 1);
+      const uint32_t nseg = (w + 31u) >> 5;
+      units = h * nseg;
+      k = pcnt[q - lo];
+      dst = base + (int64_t)poff[q - lo];
+      s_row0[wave][lane] = (uint32_t)(ci.tile_off + (int64_t)r.y * ci.GX + r.x);
+      s_gx[wave][lane] = (uint32_t)ci.GX;
+      s_w[wave][lane] = w;
+      s_nseg[wave][lane] = nseg;
+      s_m[wave][lane] = m;
+    }
+    // exclusive scans over the wave of the units and of the entries
+    uint32_t xu = units, xk = k;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t yu = (uint32_t)__shfl_up((int)xu, d, 64), yk = (uint32_t)__shfl_up((int)xk, d, 64);
+      if (lane >= d) {
+        xu += yu;
+        xk += yk;
       }
-      const uint64_t bal = __builtin_amdgcn_ballot_w64(keep);
-      if (keep) {
-        const int64_t at = dst + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        keys[at] = tile;
-        vals[at] = m;
+    }
+    const uint32_t U = (uint32_t)__shfl((int)xu, 63, 64);
+    s_ustart[wave][lane] = xu - units;
+    if (lane == 63) s_ustart[wave][64] = U;
+    s_dst[wave][lane] = dst - (int64_t)(xk - k);   // entry f of the batch: s_dst[j] + f
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    uint32_t run = 0;   // entries of the batch before this step's
+    for (uint32_t u0 = 0; u0 < U; u0 += 64u) {
+      const uint32_t u = u0 + (uint32_t)lane;
+      uint32_t bits = 0, t0 = 0, j = 0;
+      if (u < U) {
+        // the rectangle holding unit u: the last j with ustart[j] <= u
+#pragma unroll
+        for (uint32_t hstep = 32; hstep > 0; hstep >>= 1)
+          if (s_ustart[wave][j + hstep] <= u) j += hstep;
+        uint32_t seg;
+        const uint32_t ty = div_small(u - s_ustart[wave][j], s_nseg[wave][j], &seg);
+        const uint32_t x = seg << 5;
+        t0 = s_row0[wave][j] + ty * s_gx[wave][j] + x;
+        bits = alive_run(abits, t0, s_w[wave][j] - x);
       }
-      dst += __popcll(bal);
+      const uint32_t c = (uint32_t)__popc(bits);
+      uint32_t xc = c;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)xc, d, 64);
+        if (lane >= d) xc += y;
+      }
+      if (bits) {
+        int64_t at = s_dst[wave][j] + (int64_t)(run + xc - c);
+        const uint32_t mm = s_m[wave][j];
+        while (bits) {
+          keys[at] = t0 + (uint32_t)__builtin_ctz(bits);
+          vals[at] = mm;
+          ++at;
+          bits &= bits - 1u;
+        }
+      }
+      run += (uint32_t)__shfl((int)xc, 63, 64);
     }
   }
 }
@@ -1217,6 +1294,7 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
     uint32_t* poff = (uint32_t*)(ws + p.span_off);
     uint32_t* pmask = (uint32_t*)(ws + p.pmask);
     uint32_t* owner = (uint32_t*)(ws + p.span_owner);
+    uint32_t* abits = (uint32_t*)(ws + p.abits);
     const ushort4* drect = (const ushort4*)(ws + p.drect);
     uint32_t *k0, *v0;
     keygen_targets(p, ws, &k0, &v0);
@@ -1233,8 +1311,11 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
                          0, s, cams, alive, sat);
       hipLaunchKernelGGL(alive_sat_cols, dim3((unsigned)((gxm + 3) / 4), (unsigned)p.C), dim3(256),
                          0, s, cams, sat);
+      const int64_t bwaves = (p.T + 63) / 64 + 1;
+      hipLaunchKernelGGL(alive_bits_kernel, dim3((unsigned)((bwaves + 3) / 4)), dim3(256), 0, s,
+                         alive, p.T, bwaves, abits);
       hipLaunchKernelGGL(chunk_count_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams, p.C,
-                         M, lo, hi, sat, alive, flags, pcnt, pmask);
+                         M, lo, hi, sat, abits, flags, pcnt, pmask);
     }
     {
       int64_t* part = (int64_t*)(ws + p.scan_part);
@@ -1258,7 +1339,7 @@ hipError_t launch_chunk_bin(const Plan& p, int c, char* ws, hipStream_t s) {
                          p.C, M, lo, hi, pcnt, poff, pmask, owner, p.n_spans, chunk_base, chunk_n,
                          k0, v0);
       hipLaunchKernelGGL(chunk_write_big_kernel, dim3(grid), dim3(256), 0, s, order, drect, cams,
-                         p.C, M, lo, hi, alive, pcnt, poff, pmask, chunk_base, chunk_n, k0, v0);
+                         p.C, M, lo, hi, abits, pcnt, poff, pmask, chunk_base, chunk_n, k0, v0);
     }
     if ((e = hipGetLastError())) return e;
   } else {
