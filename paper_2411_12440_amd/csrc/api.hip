@@ -183,7 +183,6 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   p->span_cnt = take(4 * (p->K > 1 ? M : 1));
   p->span_off = take(4 * (p->K > 1 ? M : 1));
   p->pmask = take(4 * (p->K > 1 ? M : 1));
-  p->chunk_spans = take(8 * K);
   p->alive = take(4 * T);
   p->sat = take(4 * T);
   // depth chunks: the alive flags one bit per tile (global tile id order,

@@ -61,7 +61,7 @@ struct Plan {
   // scratch sub-allocations (byte offsets from the workspace base)
   size_t sort_keys_b = 0, sort_vals_b = 0, pre_keys_a = 0, pre_keys_b = 0, pre_vals_a = 0, pre_vals_b = 0,
          hist = 0, digit_tot = 0, scan_part = 0, span_owner = 0, span_cnt = 0, span_off = 0,
-         chunk_spans = 0, alive = 0, state = 0, done = 0, sat = 0, drect = 0, pmask = 0,
+         alive = 0, state = 0, done = 0, sat = 0, drect = 0, pmask = 0,
          abits = 0;
   // deterministic backward: per-entry sums [9][cap] and the pair-order sort
   size_t det_partial = 0, det_k0 = 0, det_v0 = 0, det_k1 = 0, det_v1 = 0, det_cnt = 0;
