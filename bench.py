@@ -61,10 +61,12 @@ def parse():
     ap.add_argument("--splats", type=int, default=3_200_000)
     ap.add_argument("--ags", type=int, default=1)
     ap.add_argument("--depth-chunks", type=int, default=7)
+    ap.add_argument("--chunk-ratio", type=int, default=0,
+                    help="factor between depth-chunk boundaries with --tune 0 (0: 2)")
     ap.add_argument("--tune", type=int, default=1,
-                    help="1: tile shape, LDS batch and depth chunks from the autotuner (timed "
-                         "before the measurement, cached per device and workload); 0: 16x16 "
-                         "tiles, one splat per thread per batch, --depth-chunks")
+                    help="1: tile shape, LDS batch, depth chunks and their boundary ratio from "
+                         "the autotuner (timed before the measurement, cached per device and "
+                         "workload); 0: 16x16 tiles, --batch, --depth-chunks, --chunk-ratio")
     ap.add_argument("--batch", type=int, default=0,
                     help="LDS batch with --tune 0 (0: one splat per thread)")
     ap.add_argument("--deterministic", type=int, default=0,
@@ -463,11 +465,12 @@ def main():
         workload_name = WORKLOADS[40]
     sp = scene_to_device(scene, dev)
     G_all = torch.from_numpy(S.upstream_grad(cams, 7004)).to(dev)
-    settings = dict(tile_w=16, tile_h=16, batch=args.batch, depth_chunks=args.depth_chunks)
+    settings = dict(tile_w=16, tile_h=16, batch=args.batch, depth_chunks=args.depth_chunks,
+                    chunk_ratio=args.chunk_ratio)
     tuned = None
     if args.tune:
         from paper_2411_12440_amd import autotune
-        log("bench: autotuning tile shape, LDS batch and depth chunks")
+        log("bench: autotuning tile shape, LDS batch, depth chunks and their ratio")
         tuner = autotune.Autotuner()
         settings = tuner.choose(cams, off, sp, G_all, 3, ags=bool(args.ags),
                                 deterministic=bool(args.deterministic))
@@ -712,6 +715,7 @@ def main():
         "config": {"workload": workload_name,
                    "views": cams.n, "pixels_per_step": P, "n_isect": n_isect,
                    "entries_built": n_built, "depth_chunks": settings["depth_chunks"],
+                   "chunk_ratio": int(settings.get("chunk_ratio", 0)) or 2,
                    "chunk_entries": chunk_entries,
                    "pairs_to_last": Q, "contributing_pairs": Qc, "ags": bool(args.ags),
                    "deterministic": bool(args.deterministic),

@@ -99,13 +99,17 @@ typedef enum {
  * depth_chunks  0 or 1: ls_bin_sort builds every tile's complete list.
  *            K in 2..12: ls_bin_sort only orders the pairs by depth and scans
  *            their tile counts; ls_rasterize_fwd then builds the lists in K
- *            chunks of that order (the first M/2^(K-1) pairs, the next
- *            M/2^(K-1), then M/2^(K-2), ..., the last M/2) and composites each
+ *            chunks of that order (with r = chunk_ratio: chunk k of 1..K
+ *            ends at M/r^(K-k), so the first M/r^(K-1) pairs, then up to
+ *            M/r^(K-2), ..., the last from M/r to M) and composites each
  *            chunk before building the next.  A chunk skips every tile whose
  *            pixels have all stopped (T would fall below t_min), so each
  *            tile's list is the prefix of its complete list that the
  *            composite can reach.  Images and gradients are identical to the
  *            complete-list mode.
+ * chunk_ratio  The factor r between successive depth-chunk boundaries
+ *            (above): 0 for the default 2, or 2..8.  A larger r builds more
+ *            entries in fewer, larger chunks.
  * deterministic  0: the backward pass sums each splat's per-tile gradients
  *            with FP64 atomics (order-dependent in the last bits).  1: it
  *            stores every list entry's per-tile sums in the workspace, orders
@@ -128,6 +132,7 @@ typedef struct ls_config {
   int32_t depth_chunks;
   int32_t kernel;
   int32_t deterministic;
+  int32_t chunk_ratio;
 } ls_config;
 
 enum {

@@ -1,7 +1,8 @@
 """Tile-shape autotuner.
 
 Chooses the raster settings that the paper leaves open — tile shape
-(tile_w x tile_h), splats staged per LDS batch and the number of depth chunks —
+(tile_w x tile_h), splats staged per LDS batch, and the number of depth chunks
+with the ratio between their boundaries —
 by timing the whole forward + backward step on the caller's own cameras and
 scene, and caches the choice in a JSON file keyed by the device, the
 splat-count bucket, the resolution set, the SH degree and the settings that
@@ -34,12 +35,15 @@ import torch
 
 from .rasterizer import Rasterizer, StepGraph
 
-# (tile_w, tile_h, batch, depth_chunks)
+# (tile_w, tile_h, batch, depth_chunks, chunk_ratio)
 DEFAULT_CANDIDATES = [
     dict(tile_w=16, tile_h=16, batch=128, depth_chunks=7),
     dict(tile_w=16, tile_h=16, batch=64, depth_chunks=7),
     dict(tile_w=16, tile_h=16, batch=128, depth_chunks=5),
     dict(tile_w=16, tile_h=16, batch=128, depth_chunks=4),
+    dict(tile_w=16, tile_h=16, batch=128, depth_chunks=6, chunk_ratio=3),
+    dict(tile_w=16, tile_h=16, batch=128, depth_chunks=5, chunk_ratio=3),
+    dict(tile_w=16, tile_h=16, batch=128, depth_chunks=4, chunk_ratio=3),
     dict(tile_w=16, tile_h=16, batch=128, depth_chunks=1),
     dict(tile_w=16, tile_h=8, batch=64, depth_chunks=7),
     dict(tile_w=32, tile_h=8, batch=128, depth_chunks=7),
@@ -58,11 +62,13 @@ def forward_threads(tile_w: int, tile_h: int) -> int:
 def effective(settings: dict) -> tuple:
     """What a setting launches: tile shape, entries staged per batch by the
     forward kernel and by the one-wave backward kernel, depth chunks (0 and
-    1 both build complete lists)."""
+    1 both build complete lists) and their boundary ratio (0 is 2; none
+    without chunks)."""
     cap = forward_threads(settings["tile_w"], settings["tile_h"])
     b = int(settings.get("batch", 0)) or cap
     k = max(1, int(settings.get("depth_chunks", 1)))
-    return (int(settings["tile_w"]), int(settings["tile_h"]), min(b, cap), min(b, 64), k)
+    r = (int(settings.get("chunk_ratio", 0)) or 2) if k > 1 else 0
+    return (int(settings["tile_w"]), int(settings["tile_h"]), min(b, cap), min(b, 64), k, r)
 
 
 def distinct(candidates) -> list:

@@ -33,7 +33,7 @@ class Config(C.Structure):
                 ("ags", C.c_int32), ("ags_arg", C.c_int32), ("ags_scope", C.c_int32),
                 ("sh_degree", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
                 ("batch", C.c_int32), ("depth_chunks", C.c_int32), ("kernel", C.c_int32),
-                ("deterministic", C.c_int32)]
+                ("deterministic", C.c_int32), ("chunk_ratio", C.c_int32)]
 
 
 KERNELS = {"linear": 0, "gaussian": 1, "laplacian": 2, "cosine": 3, "quadratic": 4}
@@ -241,7 +241,7 @@ class CamerasHost:
 def make_config(lambda_=2.5, eps2d=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
                 near=0.01, far=1e10, clip=1.3, bg=(0.0, 0.0, 0.0), ags=False, ags_arg=0,
                 ags_scope=0, sh_degree=0, tile_w=16, tile_h=16, batch=0,
-                depth_chunks=1, kernel="linear", deterministic=False) -> Config:
+                depth_chunks=1, kernel="linear", deterministic=False, chunk_ratio=0) -> Config:
     cfg = Config()
     cfg.lambda_, cfg.eps2d, cfg.alpha_min, cfg.alpha_max, cfg.t_min = lambda_, eps2d, alpha_min, alpha_max, t_min
     cfg.near_z, cfg.far_z, cfg.clip = near, far, clip
@@ -252,6 +252,7 @@ def make_config(lambda_=2.5, eps2d=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t
     cfg.depth_chunks = depth_chunks
     cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     cfg.deterministic = int(deterministic)
+    cfg.chunk_ratio = int(chunk_ratio)
     return cfg
 
 

@@ -67,6 +67,8 @@ static ls_status check_config(const ls_config* c) {
                 c->tile_w, c->tile_h);
   if (c->depth_chunks < 0 || c->depth_chunks > kMaxDepthChunks)
     return fail(LS_ERR_INVALID_ARG, "depth_chunks must be 0..%d", kMaxDepthChunks);
+  if (c->chunk_ratio != 0 && (c->chunk_ratio < 2 || c->chunk_ratio > 8))
+    return fail(LS_ERR_INVALID_ARG, "chunk_ratio must be 0 (2) or 2..8");
   // the forward kernel stages at most one entry per thread (two pixels per
   // thread from 128 pixels up), the backward kernel one per lane of its wave
   const int pix = c->tile_w * c->tile_h;
@@ -123,10 +125,15 @@ static ls_status make_plan(const ls_config* cfg, const ls_cameras* cams, int64_t
   int bits = 0;
   while (bits < 32 && ((p->T - 1) >> bits) > 0) ++bits;
   p->tile_bits = bits;
-  // depth chunks: geometric boundaries M/2^(K-1), ..., M/2, M
+  // depth chunks: geometric boundaries M/r^(K-1), ..., M/r, M
   p->K = cfg->depth_chunks < 1 ? 1 : cfg->depth_chunks;
+  const int64_t ratio = cfg->chunk_ratio == 0 ? 2 : cfg->chunk_ratio;
   p->chunk_pos.assign(p->K + 1, 0);
-  for (int c = 1; c <= p->K; ++c) p->chunk_pos[c] = p->M >> (p->K - c);
+  for (int c = 1; c <= p->K; ++c) {
+    int64_t v = p->M;
+    for (int q = c; q < p->K; ++q) v /= ratio;
+    p->chunk_pos[c] = v;
+  }
 
   // workspace layout
   size_t off = 0;

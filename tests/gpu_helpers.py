@@ -19,8 +19,8 @@ def say(*a):
 
 
 def cfg_pair(**kw):
-    """Matching oracle and library settings (depth_chunks only affects the
-    library: the oracle always builds complete lists)."""
+    """Matching oracle and library settings (depth_chunks and chunk_ratio
+    only affect the library: the oracle always builds complete lists)."""
     kw = dict(kw)
     strict = kw.pop("strict", False)
     okw = dict(lambda_=kw.get("lambda_", 2.5), ags=kw.get("ags", False),
@@ -36,7 +36,8 @@ def cfg_pair(**kw):
                clip=ocfg.clip, bg=ocfg.bg, ags=ocfg.ags, ags_arg=ocfg.ags_arg,
                ags_scope=ocfg.ags_scope, tile_w=ocfg.tile_w, tile_h=ocfg.tile_h,
                batch=kw.get("batch", 0), depth_chunks=kw.get("depth_chunks", 1),
-               kernel=ocfg.kernel, deterministic=kw.get("deterministic", False))
+               kernel=ocfg.kernel, deterministic=kw.get("deterministic", False),
+               chunk_ratio=kw.get("chunk_ratio", 0))
     return ocfg, gkw
 
 

@@ -65,7 +65,8 @@ def test_workspace_size_and_layout():
                                          ("t_min", -1.0), ("sh_degree", 4), ("ags", 2),
                                          ("batch", 100), ("near_z", -1.0),
                                          ("depth_chunks", 13), ("kernel", 5), ("kernel", -1),
-                                         ("deterministic", 2)])
+                                         ("deterministic", 2), ("chunk_ratio", 1),
+                                         ("chunk_ratio", 9), ("chunk_ratio", -1)])
 def test_invalid_config_rejected(field, value):
     from paper_2411_12440_amd import binding as B
     cfg = B.make_config()

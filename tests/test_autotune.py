@@ -45,6 +45,13 @@ def test_candidates_are_distinct_launches():
     assert at.effective(dict(tile_w=16, tile_h=16, batch=64, depth_chunks=7)) != \
         at.effective(dict(tile_w=16, tile_h=16, batch=128, depth_chunks=7))
     assert at.effective(dict(tile_w=16, tile_h=8, batch=0, depth_chunks=7))[2] == 64
+    # the chunk boundary ratio: 0 is 2, and it changes nothing without chunks
+    assert at.effective(dict(tile_w=16, tile_h=16, batch=128, depth_chunks=5, chunk_ratio=0)) == \
+        at.effective(dict(tile_w=16, tile_h=16, batch=128, depth_chunks=5, chunk_ratio=2))
+    assert at.effective(dict(tile_w=16, tile_h=16, batch=128, depth_chunks=5, chunk_ratio=3)) != \
+        at.effective(dict(tile_w=16, tile_h=16, batch=128, depth_chunks=5))
+    assert at.effective(dict(tile_w=16, tile_h=16, batch=128, depth_chunks=1, chunk_ratio=3)) == \
+        at.effective(dict(tile_w=16, tile_h=16, batch=128, depth_chunks=1))
     assert len(at.distinct(at.DEFAULT_CANDIDATES)) == len(at.DEFAULT_CANDIDATES)
     dup = at.DEFAULT_CANDIDATES + [dict(tile_w=16, tile_h=16, batch=0, depth_chunks=7)]
     assert at.distinct(dup) == at.DEFAULT_CANDIDATES

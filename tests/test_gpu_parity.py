@@ -136,15 +136,16 @@ def test_multi_camera_multi_scene(chunks):
     compare_grads(grads, go, scene)
 
 
-@pytest.mark.parametrize("chunks", [3, 7])
-def test_chunk_lists_are_prefixes_of_complete_lists(chunks):
+@pytest.mark.parametrize("chunks,ratio", [(3, 0), (7, 0), (5, 3), (4, 8)])
+def test_chunk_lists_are_prefixes_of_complete_lists(chunks, ratio):
     """Through the C ABI, the library against itself: with depth chunks each
     tile's list (its chunk segments in chunk order) is a prefix of the
     complete list that ls_bin_sort builds with one chunk, long enough to
     reach every pixel's last contributor, and the composite (image, final_T,
     last) is the same bit for bit."""
     from tests.gpu_helpers import gpu_arrays, gpu_forward, tile_lists
-    say(f"case: chunk lists against complete lists, 3 scenes, 6 cameras, {chunks} chunks")
+    say(f"case: chunk lists against complete lists, 3 scenes, 6 cameras, {chunks} chunks, "
+        f"ratio {ratio}")
     # large splats (log-scale N(-1.5, 0.6)): about 40% of the pixels run out
     # of transmittance, so the chunks leave entries unbuilt
     scs = [scenes.make_scene(n, 920 + i, -1.5, 0.6, 1) for i, n in enumerate((900, 1500, 600))]
@@ -152,7 +153,7 @@ def test_chunk_lists_are_prefixes_of_complete_lists(chunks):
     res = [(96, 64), (130, 70), (64, 64), (200, 90), (50, 120), (128, 96)]
     cams = scenes.sphere_cameras(6, 4.0, res, scene_of_cam=[0, 1, 2, 0, 1, 2])
     _, g1kw = cfg_pair(depth_chunks=1, ags=True)
-    _, gkkw = cfg_pair(depth_chunks=chunks, ags=True)
+    _, gkkw = cfg_pair(depth_chunks=chunks, ags=True, chunk_ratio=ratio)
     r1, _ = gpu_forward(scene, off, cams, g1kw)
     rk, _ = gpu_forward(scene, off, cams, gkkw)
     g1, gk = gpu_arrays(r1), gpu_arrays(rk)
@@ -182,14 +183,14 @@ def test_chunk_lists_are_prefixes_of_complete_lists(chunks):
     say(f"  {built} of {int(g1['chunk_base'][-1])} entries built; composites equal")
 
 
-@pytest.mark.parametrize("chunks", [1, 7])
-def test_workload2_binning_and_sampled_tiles(chunks):
+@pytest.mark.parametrize("chunks,ratio", [(1, 0), (7, 0), (5, 3)])
+def test_workload2_binning_and_sampled_tiles(chunks, ratio):
     """100k splats, SH3, 1280x720: binning bit-exact; composite and
     gradients compared on a seeded sample of tiles (upstream gradient zero
     elsewhere)."""
-    say(f"case: workload 2 (100k splats, SH3, 1280x720), depth chunks {chunks}")
+    say(f"case: workload 2 (100k splats, SH3, 1280x720), depth chunks {chunks}, ratio {ratio}")
     scene, off, cams = scenes.workload(2)
-    ocfg, gkw = cfg_pair(ags=True, depth_chunks=chunks)
+    ocfg, gkw = cfg_pair(ags=True, depth_chunks=chunks, chunk_ratio=ratio)
     rng = np.random.default_rng(11)
     T = 80 * 45
     tiles = np.sort(rng.choice(T, 40, replace=False))
