@@ -46,7 +46,7 @@ def _need_gpu():
 
 
 def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5, ags=True,
-                    tile=(16, 16), batch=0, graph=False):
+                    tile=(16, 16), batch=0, graph=False, chunks=7, ratio=0):
     """graph=True: after the eager checks of the forward pass, the whole step
     is captured in a StepGraph and replayed three times (eager work and a
     synchronisation between replays); every replay's image, final_T and last
@@ -58,8 +58,8 @@ def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5
     scene, off, cams = scenes.workload(k)
     N = scene.n
     deg = scene.sh_degree
-    ocfg, gkw = cfg_pair(ags=ags, depth_chunks=7, kernel=kernel, lambda_=lambda_,
-                         tile_w=tile[0], tile_h=tile[1], batch=batch)
+    ocfg, gkw = cfg_pair(ags=ags, depth_chunks=chunks, kernel=kernel, lambda_=lambda_,
+                         tile_w=tile[0], tile_h=tile[1], batch=batch, chunk_ratio=ratio)
     sp = scene_to_device(scene)
     rast = Rasterizer(cams, off, capacity=1 << 24, sh_degree=deg, **gkw)
     rast.forward(sp)
@@ -248,8 +248,15 @@ def _sampled_parity(k, views, tiles_per_view, seed, kernel="linear", lambda_=2.5
 
 
 def test_benchmark_configuration_sampled():
-    say("case: workload 40 (3.2M splats SH3, 8 x 1920x1080), AGS, depth chunks 7")
-    _sampled_parity(40, views=(0, 5), tiles_per_view=6, seed=40)
+    """The benchmark in the setting the tuner picks for it: 16x16 tiles, a
+    128-splat batch, 5 depth chunks at ratio 3."""
+    say("case: workload 40 (3.2M splats SH3, 8 x 1920x1080), AGS, depth chunks 5 at ratio 3")
+    _sampled_parity(40, views=(0, 5), tiles_per_view=6, seed=40, batch=128, chunks=5, ratio=3)
+
+
+def test_benchmark_seven_chunks_sampled():
+    say("case: workload 40, AGS, depth chunks 7 at ratio 2")
+    _sampled_parity(40, views=(2,), tiles_per_view=6, seed=43)
 
 
 def test_uneven_cameras_sampled():
@@ -280,8 +287,9 @@ def test_paper_scale_single_view_sampled():
 def test_benchmark_configuration_graph_replay_sampled():
     """The headline path: workload 40 in the benchmark's configuration, the
     whole step captured in a HIP graph and replayed."""
-    say("case: workload 40, StepGraph replays, AGS, depth chunks 7")
-    _sampled_parity(40, views=(1, 6), tiles_per_view=4, seed=42, graph=True)
+    say("case: workload 40, StepGraph replays, AGS, depth chunks 5 at ratio 3")
+    _sampled_parity(40, views=(1, 6), tiles_per_view=4, seed=42, graph=True, batch=128, chunks=5,
+                    ratio=3)
 
 
 @pytest.mark.parametrize("tile,batch", [((32, 8), 0), ((16, 8), 64), ((16, 16), 64)])
