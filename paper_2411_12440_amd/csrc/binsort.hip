@@ -931,6 +931,24 @@ __global__ __launch_bounds__(256) void chunk_write_big_kernel(
       if (bits) {
         int64_t at = s_dst[wave][j] + (int64_t)(run + xc - c);
         const uint32_t mm = s_m[wave][j];
+        // single entries up to a 16-byte boundary, then four per store
+        while (bits && (at & 3)) {
+          keys[at] = t0 + (uint32_t)__builtin_ctz(bits);
+          vals[at] = mm;
+          ++at;
+          bits &= bits - 1u;
+        }
+        while (__popc(bits) >= 4) {
+          uint32_t e[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            e[q] = t0 + (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1u;
+          }
+          *reinterpret_cast<uint4*>(keys + at) = make_uint4(e[0], e[1], e[2], e[3]);
+          *reinterpret_cast<uint4*>(vals + at) = make_uint4(mm, mm, mm, mm);
+          at += 4;
+        }
         while (bits) {
           keys[at] = t0 + (uint32_t)__builtin_ctz(bits);
           vals[at] = mm;
