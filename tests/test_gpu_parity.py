@@ -390,20 +390,20 @@ def test_backward_sums_start_at_zero(chunks):
     compare_grads(last, go, scene)
 
 
-@pytest.mark.parametrize("chunks", [1, 3])
-def test_deterministic_backward(chunks):
+@pytest.mark.parametrize("chunks,ratio", [(1, 0), (3, 0), (5, 3)])
+def test_deterministic_backward(chunks, ratio):
     """Deterministic mode: two backward passes give bitwise-equal splat
     gradients; the per-pair 2D gradients and the image of the batched call
     equal, bit for bit, those of each camera rendered alone; and the
     gradients meet the oracle bar."""
     import torch
     from paper_2411_12440_amd.rasterizer import Rasterizer
-    say(f"case: deterministic backward, 3 scenes, 6 cameras, depth chunks {chunks}")
+    say(f"case: deterministic backward, 3 scenes, 6 cameras, depth chunks {chunks}, ratio {ratio}")
     scs = [scenes.make_scene(n, 910 + i, -3.0, 0.5, 2) for i, n in enumerate((700, 1200, 400))]
     scene, off = scenes.concat_scenes(scs)
     res = [(96, 64), (130, 70), (64, 64), (200, 90), (50, 120), (128, 96)]
     cams = scenes.sphere_cameras(6, 4.0, res, scene_of_cam=[0, 1, 2, 0, 1, 2])
-    ocfg, gkw = cfg_pair(depth_chunks=chunks, deterministic=True, ags=True)
+    ocfg, gkw = cfg_pair(depth_chunks=chunks, deterministic=True, ags=True, chunk_ratio=ratio)
     G = scenes.upstream_grad(cams, 7013)
     fw = render_forward(scene, off, cams, ocfg, want_pairs=True)
     G = (G * ~pixel_flags_to_image(fw.flag, cams)).astype(np.float32)

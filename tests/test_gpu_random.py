@@ -1,6 +1,6 @@
 """Seeded random configurations of small scenes: for each seed the scene
 size, splat-size distribution, SH degree, camera set (one to four cameras of
-random size, one or two scenes), tile shape, LDS batch, depth chunks, kernel,
+random size, one or two scenes), tile shape, LDS batch, depth chunks and their ratio, kernel,
 AGS reading, strictness, background and the deterministic flag are drawn,
 and the library is compared with the oracle at the usual bars (binning
 integers bit-exact, composite and gradients within 1e-5), together with the
@@ -50,6 +50,10 @@ def draw_case(seed):
                 bg=tuple(float(x) for x in r.uniform(0, 1, 3)),
                 deterministic=bool(r.integers(2))),
     )
+    # the chunk boundary ratio from a stream of its own, so the other draws
+    # stay those of the earlier cases
+    r2 = np.random.Generator(np.random.PCG64(50_000 + seed))
+    case["kw"]["chunk_ratio"] = int(r2.choice([0, 2, 3, 4, 8]))
     return case
 
 
