@@ -82,3 +82,45 @@ def test_fit_raises_psnr(kernel):
     curve = fit.fit(400, log_every=100)
     assert curve[-1][1] > p0 + 3.0, (p0, curve)
     assert all(np.isfinite(c[2]) for c in curve)
+
+
+@pytest.mark.parametrize("kernel", ["linear", "linear_ags"])
+def test_graph_iterations_match_eager(kernel):
+    """The iteration captured in a HIP graph against eager iterations: before
+    each of three replays the eager fit takes the graph fit's variables and
+    Adam moments, and both take one step.  With the deterministic backward
+    the gradients are bitwise equal, so the variables and moments may differ
+    only by the bias corrections, which the graph forms on the device from
+    its own step count (within a few FP32 ulp); the losses agree to the
+    rounding of their FP64 sums."""
+    import torch
+    from paper_2411_12440_amd.fit2d import PatternFit
+    W, H = 64, 48
+    say(f"fit2d graph replays against eager iterations: {kernel} {W}x{H}")
+    target = scenes.pattern("stripes", 4, W, H, seed=5)
+    s0 = scenes.plane_splats(400, W, H, seed=6)
+    eager = PatternFit(target, s0, kernel=kernel, deterministic=True)
+    graph = PatternFit(target, s0, kernel=kernel, deterministic=True, graph=True)
+    for it in range(3):
+        for k in eager.raw:
+            eager.raw[k].copy_(graph.raw[k])
+        for k in eager.state:
+            for a, b in zip(eager.state[k], graph.state[k]):
+                a.copy_(b)
+        eager.step_count = graph.step_count
+        eager.step()
+        graph.step()
+        torch.cuda.synchronize()
+        le, lg = float(eager.lossv.item()), float(graph.lossv.item())
+        assert abs(le - lg) <= 1e-12 * abs(le), (it, le, lg)
+        for k in eager.raw:
+            x = graph.raw[k].cpu().numpy().astype(np.float64)
+            y = eager.raw[k].cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(x - y) <= 2.0 ** -21 * np.abs(y) + 1e-9), (it, k)
+        for k in eager.state:
+            for a, b, nm in zip(graph.state[k], eager.state[k], ("m", "v")):
+                x, y = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+                assert np.all(np.abs(x - y) <= 2.0 ** -21 * np.abs(y) + 1e-20), (it, k, nm)
+    assert graph.step_count == 3 and int(graph._step_dev.item()) == 4
+    assert not graph.rast.overflowed()
+
