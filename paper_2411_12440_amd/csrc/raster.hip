@@ -358,10 +358,10 @@ template <int TW, int TH>
 constexpr int raster_threads() { return TW * TH / raster_ppl<TW, TH>(); }
 
 // The forward pass is bound by the latency of its global reads (tile
-// state, staged records): seven waves per SIMD instead of the five its
+// state, staged records): six waves per SIMD instead of the five its
 // registers would allow (a few values live across the loop go to scratch).
 template <int TW, int TH, int KF>
-__global__ __launch_bounds__((raster_threads<TW, TH>())) __attribute__((amdgpu_waves_per_eu(7)))
+__global__ __launch_bounds__((raster_threads<TW, TH>())) __attribute__((amdgpu_waves_per_eu(6)))
 void raster_fwd_kernel(
     const CamInfo* __restrict__ cams, int C, const int64_t* __restrict__ ranges_all, int64_t T_all,
     int c, int K, const int64_t* __restrict__ chunk_base, const uint32_t* __restrict__ vals,
